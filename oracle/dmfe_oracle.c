@@ -1,0 +1,657 @@
+/*
+ * dmfe_oracle.c -- plain FP64 CPU oracle for the two-time DMFE of the mixed
+ * spherical p-spin model (DYNAMITE, arXiv 2604.06309).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file.  Only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark use it.  It shares no code, header, table or constant
+ * generator with the HIP path.
+ *
+ * What it computes (each function cites the passage it follows):
+ *   - the model: f(q) = sum_p a_p^2 q^p / 2 and its derivatives (Sec. 2.1,
+ *     covariance equation);
+ *   - a uniform-grid solver: classical RK4 in t with trapezoid history
+ *     integrals over the stored causal triangle (the direct O(N^3) baseline of
+ *     Sec. 2.3; the scheme itself is not printed in the paper, see the
+ *     readings list in the design notes);
+ *   - the theta-grid of eq. (theta) at alpha = 0 and its inverse index map;
+ *   - one evaluation of the right-hand side on the theta-grid: index-space
+ *     Lagrange interpolation in theta (Sec. 3.3), cubic Hermite interpolation
+ *     in t (Sec. 3.3), the change of variables phi1 = theta_i theta_j and
+ *     phi2 = theta_j + (1 - theta_j) theta_i and the quadrature sums of
+ *     eq. (int) (Sec. 3.4), mu(t) and E(t) (Sec. 2.1);
+ *   - the sparsification residual and greedy selection (Sec. 3.6);
+ *   - the adaptive driver: Dormand-Prince then SSPRK(10,4), the 1-norm error
+ *     and the step-size rules of Sec. 3.5.
+ *
+ * Everything is double precision, written as loops in the order of the
+ * definitions, without blocking or fusion.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_MAX_TERMS 8
+
+typedef struct {
+    int n_terms;
+    int p[OR_MAX_TERMS];
+    double a2[OR_MAX_TERMS]; /* the a_p^2 */
+    double T;
+    double beta0;
+} or_model;
+
+/* ------------------------------------------------------------------ model */
+/* f(q) = sum a_p^2 q^p / 2  (Sec. 2.1, covariance function). */
+double or_f(const or_model *m, double q) {
+    double s = 0.0;
+    for (int k = 0; k < m->n_terms; ++k) s += 0.5 * m->a2[k] * pow(q, m->p[k]);
+    return s;
+}
+/* f'(q) = sum a_p^2 p q^(p-1) / 2 */
+double or_f1(const or_model *m, double q) {
+    double s = 0.0;
+    for (int k = 0; k < m->n_terms; ++k)
+        s += 0.5 * m->a2[k] * m->p[k] * pow(q, m->p[k] - 1);
+    return s;
+}
+/* f''(q) = sum a_p^2 p (p-1) q^(p-2) / 2 */
+double or_f2(const or_model *m, double q) {
+    double s = 0.0;
+    for (int k = 0; k < m->n_terms; ++k)
+        if (m->p[k] >= 2) s += 0.5 * m->a2[k] * m->p[k] * (m->p[k] - 1) * pow(q, m->p[k] - 2);
+    return s;
+}
+
+/* ======================================================================
+ * Uniform-grid solver.
+ * Storage: packed lower triangle, row n holds X[n][0..n] at offset n(n+1)/2.
+ * ====================================================================== */
+static inline size_t tri(int n, int k) { return (size_t)n * (n + 1) / 2 + k; }
+
+/* Trapezoid weight of node m on the nodes lo..hi with spacing h (zero if lo == hi). */
+static double trap_w(int m, int lo, int hi, double h) {
+    if (hi <= lo) return 0.0;
+    if (m == lo || m == hi) return 0.5 * h;
+    return h;
+}
+
+/*
+ * Right-hand side of the DMFE (eq. genericDMFE with the -mu terms, kernels
+ * K = f''(C)R, D = f'(C), forcing F_C = beta0 f'(C(t,0)) C(t',0) and mu of
+ * Sec. 2.1) for the row C(t, t_k), R(t, t_k), k = 0..n, at t = t_n + delta.
+ * The integrals over s are trapezoid sums on the stored nodes t_0..t_n plus
+ * the partial panel [t_n, t] whose right end is the diagonal s = t, where
+ * C(t,t) = R(t,t^-) = 1.
+ */
+static void uni_rhs(const or_model *m, int n, double h, double delta,
+                    const double *Ct, const double *Rt,
+                    const double *c, const double *r, double *dc, double *dr) {
+    double *W = (double *)malloc(sizeof(double) * (n + 1));
+    for (int q = 0; q <= n; ++q) W[q] = trap_w(q, 0, n, h);
+    W[n] += 0.5 * delta;
+    const double Ws = 0.5 * delta;
+    const double f1one = or_f1(m, 1.0), f2one = or_f2(m, 1.0);
+
+    /* mu(t) = T + int_0^t [K C + D R](t,s) ds + F_C(t,t) */
+    double mu = m->T;
+    for (int q = 0; q <= n; ++q)
+        mu += W[q] * (or_f2(m, c[q]) * r[q] * c[q] + or_f1(m, c[q]) * r[q]);
+    mu += Ws * (f2one + f1one);
+    mu += m->beta0 * or_f1(m, c[0]) * c[0];
+
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int k = 0; k <= n; ++k) {
+        /* int_0^t K(t,s) C(s,t_k) ds, C symmetric */
+        double A = 0.0;
+        for (int q = 0; q <= n; ++q) {
+            double Cqk = (q >= k) ? Ct[tri(q, k)] : Ct[tri(k, q)];
+            A += W[q] * or_f2(m, c[q]) * r[q] * Cqk;
+        }
+        A += Ws * f2one * c[k];
+        /* int_0^{t_k} D(t,s) R(t_k,s) ds */
+        double B = 0.0;
+        for (int q = 0; q <= k; ++q) B += trap_w(q, 0, k, h) * or_f1(m, c[q]) * Rt[tri(k, q)];
+        /* int_{t_k}^t K(t,s) R(s,t_k) ds */
+        double Q = 0.0;
+        for (int q = k; q <= n; ++q) {
+            double w = trap_w(q, k, n, h) + (q == n ? 0.5 * delta : 0.0);
+            Q += w * or_f2(m, c[q]) * r[q] * Rt[tri(q, k)];
+        }
+        Q += Ws * f2one * r[k];
+        dc[k] = -mu * c[k] + A + B + m->beta0 * or_f1(m, c[0]) * Ct[tri(k, 0)];
+        dr[k] = -mu * r[k] + Q;
+    }
+    free(W);
+}
+
+/* E(t_n) = -int_0^{t_n} f'(C(t_n,s)) R(t_n,s) ds - beta0 f(C(t_n,0))  (Sec. 2.1) */
+static double uni_energy(const or_model *m, int n, double h, const double *Ct, const double *Rt) {
+    double e = 0.0;
+    for (int q = 0; q <= n; ++q) e += trap_w(q, 0, n, h) * or_f1(m, Ct[tri(n, q)]) * Rt[tri(n, q)];
+    return -e - m->beta0 * or_f(m, Ct[tri(n, 0)]);
+}
+
+/*
+ * Classical RK4 over N steps of size h from C(0,0) = R(0,0^-) = 1.
+ * C, R: packed triangles with room for N+1 rows.  E: N+1 energies.
+ * Returns 0.
+ */
+int or_uniform_solve(const or_model *m, double h, int N, double *C, double *R, double *E) {
+    C[0] = 1.0;
+    R[0] = 1.0;
+    E[0] = uni_energy(m, 0, h, C, R);
+    int cap = N + 2;
+    double *y = malloc(sizeof(double) * 2 * cap), *ys = malloc(sizeof(double) * 2 * cap);
+    double *k1 = malloc(sizeof(double) * 2 * cap), *k2 = malloc(sizeof(double) * 2 * cap);
+    double *k3 = malloc(sizeof(double) * 2 * cap), *k4 = malloc(sizeof(double) * 2 * cap);
+    for (int n = 0; n < N; ++n) {
+        int w = n + 1; /* unknowns k = 0..n for each field */
+        for (int k = 0; k <= n; ++k) {
+            y[k] = C[tri(n, k)];
+            y[cap + k] = R[tri(n, k)];
+        }
+        uni_rhs(m, n, h, 0.0, C, R, y, y + cap, k1, k1 + cap);
+        for (int k = 0; k < w; ++k) {
+            ys[k] = y[k] + 0.5 * h * k1[k];
+            ys[cap + k] = y[cap + k] + 0.5 * h * k1[cap + k];
+        }
+        uni_rhs(m, n, h, 0.5 * h, C, R, ys, ys + cap, k2, k2 + cap);
+        for (int k = 0; k < w; ++k) {
+            ys[k] = y[k] + 0.5 * h * k2[k];
+            ys[cap + k] = y[cap + k] + 0.5 * h * k2[cap + k];
+        }
+        uni_rhs(m, n, h, 0.5 * h, C, R, ys, ys + cap, k3, k3 + cap);
+        for (int k = 0; k < w; ++k) {
+            ys[k] = y[k] + h * k3[k];
+            ys[cap + k] = y[cap + k] + h * k3[cap + k];
+        }
+        uni_rhs(m, n, h, h, C, R, ys, ys + cap, k4, k4 + cap);
+        for (int k = 0; k < w; ++k) {
+            C[tri(n + 1, k)] = y[k] + h / 6.0 * (k1[k] + 2.0 * k2[k] + 2.0 * k3[k] + k4[k]);
+            R[tri(n + 1, k)] = y[cap + k] +
+                               h / 6.0 * (k1[cap + k] + 2.0 * k2[cap + k] + 2.0 * k3[cap + k] + k4[cap + k]);
+        }
+        C[tri(n + 1, n + 1)] = 1.0;
+        R[tri(n + 1, n + 1)] = 1.0;
+        E[n + 1] = uni_energy(m, n + 1, h, C, R);
+    }
+    free(y); free(ys); free(k1); free(k2); free(k3); free(k4);
+    return 0;
+}
+
+/* One right-hand-side evaluation of the uniform scheme (exported for tests). */
+void or_uniform_rhs(const or_model *m, int n, double h, double delta, const double *C,
+                    const double *R, const double *c, const double *r, double *dc, double *dr) {
+    uni_rhs(m, n, h, delta, C, R, c, r, dc, dr);
+}
+
+/* ======================================================================
+ * theta-grid (eq. theta at alpha = 0).
+ * ====================================================================== */
+
+/* gamma = -W_{-1}(-1/t_max), i.e. the root gamma > 1 of gamma - ln(gamma) = ln(t_max). */
+double or_gamma(double tmax) {
+    double lt = log(tmax);
+    double g = lt + log(lt) + 1.0;
+    for (int it = 0; it < 100; ++it) {
+        double F = g - log(g) - lt;
+        double dF = 1.0 - 1.0 / g;
+        double gn = g - F / dF;
+        if (fabs(gn - g) <= 1e-16 * gn) { g = gn; break; }
+        g = gn;
+    }
+    return g;
+}
+
+/*
+ * theta_i for i = 0..L-1 (paper index i+1) and the complements 1 - theta_i.
+ * The numerator atan(e^g) - atan(e^{-g y}) is evaluated through
+ * atan(a) - atan(b) = atan((a - b)/(1 + ab)) (a, b > 0) with
+ * a - b = -e^g expm1(-g (1 + y)), which keeps full relative precision near
+ * theta = 0.  Points with theta > 1/2 are taken from the symmetry
+ * theta(-y) = 1 - theta(y) of eq. (theta) at alpha = 0.
+ */
+void or_theta_grid(int L, double gamma, double *th, double *thc) {
+    double D = atan(exp(gamma)) - atan(exp(-gamma));
+    for (int i = 0; i < L; ++i) {
+        if (2 * i + 1 - L > 0) continue; /* upper half below */
+        double y = (double)(2 * i + 1 - L) / (double)(L - 1);
+        double num = -exp(gamma) * expm1(-gamma * (1.0 + y)) / (1.0 + exp(gamma * (1.0 - y)));
+        th[i] = atan(num) / D;
+        thc[i] = 1.0 - th[i];
+    }
+    for (int i = 0; i < L; ++i) {
+        if (2 * i + 1 - L <= 0) continue;
+        thc[i] = th[L - 1 - i];
+        th[i] = 1.0 - thc[i];
+    }
+}
+
+typedef struct {
+    int L, s;
+    double gamma, D;
+    const double *th, *thc, *nu;
+} or_grid;
+
+/*
+ * Continuous 0-based index x(theta) of the grid, the inverse of eq. (theta):
+ * with T = tan(theta D), 1 + y = [ln(1 + e^g T) - ln(1 - e^{-g} T)] / g and
+ * x = (L - 1)(1 + y)/2.  Used for theta <= 1/2; above, x = L-1 - x(1-theta)
+ * with the complement supplied by the caller.
+ */
+static double or_xhalf(const or_grid *g, double th) {
+    double T = tan(th * g->D);
+    return 0.5 * (g->L - 1) * (log1p(exp(g->gamma) * T) - log1p(-exp(-g->gamma) * T)) / g->gamma;
+}
+static double or_xmap(const or_grid *g, double th, double thc) {
+    if (th <= 0.5) return or_xhalf(g, th);
+    return (double)(g->L - 1) - or_xhalf(g, thc);
+}
+double or_index_of(int L, double gamma, double th, double thc) {
+    or_grid g = {L, 10, gamma, atan(exp(gamma)) - atan(exp(-gamma)), 0, 0, 0};
+    return or_xmap(&g, th, thc);
+}
+
+/*
+ * s-point Lagrange interpolation on the equidistant index coordinate
+ * (Sec. 3.3, "index interpolation"): nodes base..base+s-1 with
+ * base = floor(x) - (s-1)/2 clamped to [0, L-s], weights
+ * w_k = prod_{l != k} (x - node_l)/(node_k - node_l).
+ */
+static double or_lagr(const or_grid *g, const double *row, double x) {
+    int s = g->s;
+    int base = (int)floor(x) - (s - 1) / 2;
+    if (base < 0) base = 0;
+    if (base > g->L - s) base = g->L - s;
+    double v = 0.0;
+    for (int k = 0; k < s; ++k) {
+        double w = 1.0;
+        for (int l = 0; l < s; ++l)
+            if (l != k) w *= (x - (double)(base + l)) / (double)(k - l);
+        v += w * row[base + k];
+    }
+    return v;
+}
+
+/* Stored history in the oracle's own layout: four [M][L] arrays. */
+typedef struct {
+    int M;           /* slices 0..M-1 */
+    int nb;          /* slices 0..nb-1 carry a stored d/dt (nb = M-1 at stage 1, M later) */
+    const double *t; /* t_n */
+    const double *C, *R, *dC, *dR;
+    double tcur;                /* current stage time t */
+    const double *yC, *yR;      /* current stage slice C(t, theta_i t), R(t, theta_i t) */
+} or_hist;
+
+/* value of a [M][L] history array at slice n, at node i (x < 0) or index x */
+static double slice_at(const or_grid *g, const double *arr, int n, int node, double x) {
+    const double *row = arr + (size_t)n * g->L;
+    return node >= 0 ? row[node] : or_lagr(g, row, x);
+}
+
+/*
+ * (C, R)(tau, theta-coordinate) for 0 <= tau <= t, the theta-coordinate being
+ * the grid node `node` (node >= 0) or the continuous index x.
+ *  - tau inside the stored slices with known d/dt: cubic Hermite in t between
+ *    the bracketing slices, theta-interpolating value and d/dt on each
+ *    (Sec. 3.3, the 2-D stencil for I_2);
+ *  - tau above the last slice with known d/dt (inside the current step): the
+ *    quadratic in t through value and d/dt at that slice and the value of the
+ *    current stage slice at t.
+ */
+static void or_hist_at(const or_grid *g, const or_hist *H, double tau, int node, double x, double out[2]) {
+    const double *cur[2] = {H->yC, H->yR};
+    if (H->nb == 0) { /* only t = t_0 exists */
+        for (int f = 0; f < 2; ++f) out[f] = node >= 0 ? cur[f][node] : or_lagr(g, cur[f], x);
+        return;
+    }
+    const double *val[2] = {H->C, H->R};
+    const double *der[2] = {H->dC, H->dR};
+    int b = H->nb - 1;
+    double tb = H->t[b];
+    if (tau <= tb) {
+        if (b == 0) {
+            for (int f = 0; f < 2; ++f) out[f] = slice_at(g, val[f], 0, node, x);
+            return;
+        }
+        int m = 0;
+        while (m + 1 < b && H->t[m + 1] <= tau) ++m;
+        double h = H->t[m + 1] - H->t[m];
+        double u = (tau - H->t[m]) / h;
+        double h00 = 2 * u * u * u - 3 * u * u + 1, h10 = u * u * u - 2 * u * u + u;
+        double h01 = -2 * u * u * u + 3 * u * u, h11 = u * u * u - u * u;
+        for (int f = 0; f < 2; ++f) {
+            double y0 = slice_at(g, val[f], m, node, x), d0 = slice_at(g, der[f], m, node, x);
+            double y1 = slice_at(g, val[f], m + 1, node, x), d1 = slice_at(g, der[f], m + 1, node, x);
+            out[f] = h00 * y0 + h10 * h * d0 + h01 * y1 + h11 * h * d1;
+        }
+    } else {
+        double h = H->tcur - tb;
+        double u = (tau - tb) / h;
+        for (int f = 0; f < 2; ++f) {
+            double yb = slice_at(g, val[f], b, node, x), db = slice_at(g, der[f], b, node, x);
+            double yc = node >= 0 ? cur[f][node] : or_lagr(g, cur[f], x);
+            out[f] = yb * (1.0 - u * u) + db * h * (u - u * u) + yc * u * u;
+        }
+    }
+}
+
+/* mu(t) and E(t) of a slice (Sec. 2.1): s = theta t, ds = t dtheta, quadrature nu. */
+void or_mu_energy(const or_model *m, int L, const double *nu, double t, const double *yC,
+                  const double *yR, double *mu, double *E) {
+    double sk = 0.0, se = 0.0;
+    for (int i = 0; i < L; ++i) {
+        sk += nu[i] * (or_f2(m, yC[i]) * yR[i] * yC[i] + or_f1(m, yC[i]) * yR[i]);
+        se += nu[i] * or_f1(m, yC[i]) * yR[i];
+    }
+    *mu = m->T + t * sk + m->beta0 * or_f1(m, yC[0]) * yC[0];
+    *E = -t * se - m->beta0 * or_f(m, yC[0]);
+}
+
+/*
+ * Right-hand side on the theta-grid: d/dt of C(t, theta_j t) and
+ * R(t, theta_j t) for the rows listed in `rows` (all rows if rows == NULL).
+ *
+ * For row j (t' = theta_j t) and quadrature node i, with the readings of
+ * Sec. 3.3-3.4 (Jacobians theta_j and 1 - theta_j restored):
+ *   a = (C,R)(t, theta_i theta_j t)     phi1 = theta_i theta_j
+ *   b = (C,R)(t, phi t)                 phi  = theta_j + (1-theta_j) theta_i
+ *   c = (C,R)(t', theta_i t')           row Hermite in t
+ *   d = (C,R)(phi t, psi phi t)         psi  = theta_j / phi, 2-D stencil
+ * and the DMFE at (t, t') and at the swapped arguments (t', t):
+ *   d1C = -mu C + t[th S1 + th S2 + (1-th) S3] + beta0 f'(C(t,0)) C(t',0)
+ *   d1R = -mu R + t (1-th) S4
+ *   mu' = T + t th S9 + beta0 f'(C(t',0)) C(t',0)
+ *   d2C = -mu' C + t[th S5 + th S6 + (1-th) S7] + 2T R + beta0 f'(C(t',0)) C(t,0)
+ *   d2R =  mu' R - t (1-th) S8            (left-resolvent form of the R equation)
+ *   dC/dt|_theta = d1C + th d2C,  dR/dt|_theta = d1R + th d2R.
+ * Output rows not listed are left untouched.  sums9 (optional) receives the
+ * nine sums per listed row as [row][9].  The diagonal row j = L-1 is returned
+ * as computed (callers pin it).
+ */
+int or_theta_rhs(const or_model *m, const or_grid *g, const or_hist *H, double mu,
+                 const int *rows, int nrows, double *outC, double *outR, double *sums9) {
+    int L = g->L;
+    int nr = rows ? nrows : L;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int r = 0; r < nr; ++r) {
+        int j = rows ? rows[r] : r;
+        double thj = g->th[j], thcj = g->thc[j], t = H->tcur, tp = thj * t;
+        double S[9] = {0};
+        for (int i = 0; i < L; ++i) {
+            double thi = g->th[i], thci = g->thc[i], w = g->nu[i];
+            double xa = or_xmap(g, thi * thj, thci + thi * thcj);
+            double aC = or_lagr(g, H->yC, xa), aR = or_lagr(g, H->yR, xa);
+            double phi = thj + thcj * thi, phic = thcj * thci;
+            double xb = or_xmap(g, phi, phic);
+            double bC = or_lagr(g, H->yC, xb), bR = or_lagr(g, H->yR, xb);
+            double cv[2];
+            or_hist_at(g, H, tp, i, 0.0, cv);
+            double psi = 0.0, psic = 1.0; /* psi = 0/0 := 0 at i = j = 0 */
+            if (phi > 0.0) { psi = thj / phi; psic = thcj * thi / phi; }
+            double xd = or_xmap(g, psi, psic);
+            double dv[2];
+            or_hist_at(g, H, phi * t, -1, xd, dv);
+            double cC = cv[0], cR = cv[1], dC = dv[0], dR = dv[1];
+            S[0] += w * or_f2(m, aC) * aR * cC;
+            S[1] += w * or_f1(m, aC) * cR;
+            S[2] += w * or_f2(m, bC) * bR * dC;
+            S[3] += w * or_f2(m, bC) * bR * dR;
+            S[4] += w * or_f2(m, cC) * cR * aC;
+            S[5] += w * or_f1(m, cC) * aR;
+            S[6] += w * or_f1(m, dC) * bR;
+            S[7] += w * bR * or_f2(m, dC) * dR;
+            S[8] += w * (or_f2(m, cC) * cR * cC + or_f1(m, cC) * cR);
+        }
+        double c0[2];
+        or_hist_at(g, H, tp, 0, 0.0, c0); /* C(t', 0) */
+        double Ct0 = H->yC[0];            /* C(t, 0) */
+        double Cj = H->yC[j], Rj = H->yR[j];
+        double d1C = -mu * Cj + t * (thj * S[0] + thj * S[1] + thcj * S[2]) + m->beta0 * or_f1(m, Ct0) * c0[0];
+        double d1R = -mu * Rj + t * thcj * S[3];
+        double mup = m->T + t * thj * S[8] + m->beta0 * or_f1(m, c0[0]) * c0[0];
+        double d2C = -mup * Cj + t * (thj * S[4] + thj * S[5] + thcj * S[6]) + 2.0 * m->T * Rj +
+                     m->beta0 * or_f1(m, c0[0]) * Ct0;
+        double d2R = mup * Rj - t * thcj * S[7];
+        outC[j] = d1C + thj * d2C;
+        outR[j] = d1R + thj * d2R;
+        if (sums9)
+            for (int q = 0; q < 9; ++q) sums9[(size_t)r * 9 + q] = S[q];
+    }
+    return 0;
+}
+
+/* Interpolated history value (C, R) at (tau, index x) -- exported for tests. */
+void or_hist_value(const or_grid *g, const or_hist *H, double tau, int node, double x, double *out2) {
+    or_hist_at(g, H, tau, node, x, out2);
+}
+
+/* ======================================================================
+ * Sparsification (Sec. 3.6).
+ * ====================================================================== */
+
+/* Integral over [ta, tb] of the cubic Hermite interpolant through (ya, da), (yb, db). */
+static double herm_int(double ta, double tb, double ya, double da, double yb, double db) {
+    double h = tb - ta;
+    return h * (ya + yb) / 2.0 + h * h * (da - db) / 12.0;
+}
+
+/*
+ * eps_n = sum_i |Delta_n^C(theta_i)| + |Delta_n^R(theta_i)|, where Delta_n is
+ * the integral over [t_{n-1}, t_{n+1}] of the Hermite interpolant with slice n
+ * minus the one without it.  Computed for n = 1..M-2; eps[0] = eps[M-1] = -1.
+ */
+void or_sparsify_residuals(int M, int L, const double *t, const double *C, const double *R,
+                           const double *dC, const double *dR, double *eps) {
+    eps[0] = -1.0;
+    if (M >= 1) eps[M - 1] = -1.0;
+    for (int n = 1; n + 1 < M; ++n) {
+        double e = 0.0;
+        const double *vals[2] = {C, R}, *ders[2] = {dC, dR};
+        for (int f = 0; f < 2; ++f) {
+            const double *Y = vals[f], *Dd = ders[f];
+            for (int i = 0; i < L; ++i) {
+                size_t a = (size_t)(n - 1) * L + i, c = (size_t)n * L + i, b = (size_t)(n + 1) * L + i;
+                double with = herm_int(t[n - 1], t[n], Y[a], Dd[a], Y[c], Dd[c]) +
+                              herm_int(t[n], t[n + 1], Y[c], Dd[c], Y[b], Dd[b]);
+                double without = herm_int(t[n - 1], t[n + 1], Y[a], Dd[a], Y[b], Dd[b]);
+                e += fabs(with - without);
+            }
+        }
+        eps[n] = e;
+    }
+}
+
+/*
+ * One greedy pass over candidates n = 1..last: drop n when eps[n] < thr and
+ * continue at n+2, otherwise continue at n+1.  drop[n] = 1 for dropped slices.
+ * Returns the number dropped.
+ */
+int or_sparsify_select(int M, int last, const double *eps, double thr, int *drop) {
+    int cnt = 0;
+    for (int n = 0; n < M; ++n) drop[n] = 0;
+    int n = 1;
+    while (n <= last) {
+        if (eps[n] < thr) {
+            drop[n] = 1;
+            ++cnt;
+            n += 2;
+        } else {
+            n += 1;
+        }
+    }
+    return cnt;
+}
+
+/* ======================================================================
+ * Adaptive driver (Sec. 3.5): DP5 until its stability boundary, then
+ * SSPRK(10,4); 1-norm error; accept / x0.9 / x1.01 / revert-10-and-halve.
+ * ====================================================================== */
+
+typedef struct {
+    int S;                 /* stages */
+    double A[10][10], b[10], e[10], c[10]; /* e = b - bhat */
+} or_tableau;
+
+typedef struct {
+    double eps, dt0, dt_min;
+    double rho;            /* 4 sqrt(f''(1)) */
+    double dp5_limit, ssp_limit;
+    int M_cap;
+    int auto_passes;
+    const or_tableau *dp5, *ssp;
+} or_adapt;
+
+typedef struct {
+    /* history: slots in logical order, capacity M_cap */
+    double *t, *C, *R, *dC, *dR;
+    int M, nb_last_valid; /* nb_last_valid unused in the oracle: stage 1 always recomputes */
+    double dt;
+    int scheme;           /* 0 = DP5, 1 = SSPRK(10,4) */
+    int64_t accepted, rejected, reverts, removed, n_sparsify;
+    double last_eps;
+} or_state;
+
+static void drop_slices(or_state *s, int L, const int *drop) {
+    int w = 0;
+    for (int n = 0; n < s->M; ++n) {
+        if (drop[n]) continue;
+        if (w != n) {
+            s->t[w] = s->t[n];
+            memcpy(s->C + (size_t)w * L, s->C + (size_t)n * L, sizeof(double) * L);
+            memcpy(s->R + (size_t)w * L, s->R + (size_t)n * L, sizeof(double) * L);
+            memcpy(s->dC + (size_t)w * L, s->dC + (size_t)n * L, sizeof(double) * L);
+            memcpy(s->dR + (size_t)w * L, s->dR + (size_t)n * L, sizeof(double) * L);
+        }
+        ++w;
+    }
+    s->M = w;
+}
+
+/* One sparsification pass over the protected candidate range n = 1..M-12. */
+int or_sparsify_pass(or_state *s, int L, double eps_tol) {
+    int M = s->M;
+    if (M < 13) return 0;
+    double *eps = malloc(sizeof(double) * M);
+    int *drop = malloc(sizeof(int) * M);
+    or_sparsify_residuals(M, L, s->t, s->C, s->R, s->dC, s->dR, eps);
+    int cnt = or_sparsify_select(M, M - 12, eps, eps_tol / 10.0, drop);
+    drop_slices(s, L, drop);
+    free(eps);
+    free(drop);
+    s->removed += cnt;
+    s->n_sparsify += 1;
+    return cnt;
+}
+
+/* status codes (same meaning as the product's, defined independently) */
+#define OR_OK 0
+#define OR_DONE 1
+#define OR_CAPACITY (-3)
+#define OR_UNDERFLOW (-4)
+#define OR_NONFINITE (-5)
+
+/*
+ * Advance until t >= t_target or max_steps steps (accepted + rejected) have
+ * been taken.  On entry s holds M >= 1 slices; slice M-1 is the state.
+ */
+int or_adaptive_run(const or_model *m, const or_grid *g, const or_adapt *ad, or_state *s,
+                    double t_target, int64_t max_steps) {
+    int L = g->L;
+    double *y0 = malloc(sizeof(double) * 2 * L), *ys = malloc(sizeof(double) * 2 * L);
+    double *k = malloc(sizeof(double) * 2 * L * 10);
+    int status = OR_OK;
+    for (int64_t step = 0; step < max_steps; ++step) {
+        int M = s->M;
+        double tn = s->t[M - 1];
+        if (tn >= t_target) break;
+        if (M >= ad->M_cap) {
+            int got = 0;
+            for (int p = 0; p < ad->auto_passes; ++p) got += or_sparsify_pass(s, L, ad->eps);
+            if (got == 0) { status = OR_CAPACITY; break; }
+            M = s->M;
+        }
+        const or_tableau *tb = s->scheme == 0 ? ad->dp5 : ad->ssp;
+        double dt = s->dt;
+        memcpy(y0, s->C + (size_t)(M - 1) * L, sizeof(double) * L);
+        memcpy(y0 + L, s->R + (size_t)(M - 1) * L, sizeof(double) * L);
+        for (int st = 0; st < tb->S; ++st) {
+            for (int q = 0; q < 2 * L; ++q) {
+                double acc = y0[q];
+                for (int l = 0; l < st; ++l) acc += dt * tb->A[st][l] * k[(size_t)l * 2 * L + q];
+                ys[q] = acc;
+            }
+            ys[L - 1] = 1.0;
+            ys[2 * L - 1] = 1.0;
+            double tst = tn + tb->c[st] * dt;
+            or_hist H = {M, st == 0 ? M - 1 : M, s->t, s->C, s->R, s->dC, s->dR, tst, ys, ys + L};
+            double mu, E;
+            or_mu_energy(m, L, g->nu, tst, ys, ys + L, &mu, &E);
+            double *kc = k + (size_t)st * 2 * L;
+            or_theta_rhs(m, g, &H, mu, NULL, 0, kc, kc + L, NULL);
+            kc[L - 1] = 0.0;
+            kc[2 * L - 1] = 0.0;
+            if (st == 0) { /* the stage-1 derivative is the stored d/dt of slice M-1 */
+                memcpy(s->dC + (size_t)(M - 1) * L, kc, sizeof(double) * L);
+                memcpy(s->dR + (size_t)(M - 1) * L, kc + L, sizeof(double) * L);
+            }
+        }
+        double err = 0.0;
+        for (int q = 0; q < 2 * L; ++q) {
+            double acc = 0.0;
+            for (int l = 0; l < tb->S; ++l) acc += tb->e[l] * k[(size_t)l * 2 * L + q];
+            err += fabs(dt * acc);
+        }
+        s->last_eps = err;
+        if (!isfinite(err)) { status = OR_NONFINITE; break; }
+        if (err > 2.0 * ad->eps) {
+            int nrev = M - 1 < 10 ? M - 1 : 10;
+            s->M -= nrev;
+            s->rejected += 1;
+            s->reverts += 1;
+            s->dt = 0.5 * dt;
+        } else {
+            for (int q = 0; q < 2 * L; ++q) {
+                double acc = y0[q];
+                for (int l = 0; l < tb->S; ++l) acc += dt * tb->b[l] * k[(size_t)l * 2 * L + q];
+                ys[q] = acc;
+            }
+            ys[L - 1] = 1.0;
+            ys[2 * L - 1] = 1.0;
+            int n = s->M;
+            s->t[n] = tn + dt;
+            memcpy(s->C + (size_t)n * L, ys, sizeof(double) * L);
+            memcpy(s->R + (size_t)n * L, ys + L, sizeof(double) * L);
+            memset(s->dC + (size_t)n * L, 0, sizeof(double) * L);
+            memset(s->dR + (size_t)n * L, 0, sizeof(double) * L);
+            s->M = n + 1;
+            s->accepted += 1;
+            if (err > ad->eps) s->dt = 0.9 * dt;
+            else if (err < 0.5 * ad->eps) s->dt = 1.01 * dt;
+            if (s->scheme == 0 && s->dt * ad->rho >= ad->dp5_limit) {
+                s->scheme = 1;
+                s->dt *= 0.5;
+            }
+            if (s->scheme == 1 && s->dt * ad->rho > ad->ssp_limit) s->dt = ad->ssp_limit / ad->rho;
+        }
+        if (s->dt < ad->dt_min) { status = OR_UNDERFLOW; break; }
+    }
+    free(y0); free(ys); free(k);
+    if (status == OR_OK && s->t[s->M - 1] >= t_target) status = OR_DONE;
+    return status;
+}
+
+/* struct sizes, so the Python side can check its ctypes mirrors */
+int or_sizeof(int which) {
+    switch (which) {
+    case 0: return (int)sizeof(or_model);
+    case 1: return (int)sizeof(or_grid);
+    case 2: return (int)sizeof(or_hist);
+    case 3: return (int)sizeof(or_tableau);
+    case 4: return (int)sizeof(or_adapt);
+    case 5: return (int)sizeof(or_state);
+    }
+    return -1;
+}

@@ -1,0 +1,270 @@
+/*
+ * dmfe.h -- C-ABI of the MI355X-native solver for the two-time dynamical
+ * mean-field equations (DMFE) of the mixed spherical p-spin model
+ * (DYNAMITE, arXiv 2604.06309).
+ *
+ * The model (Sec. 2.1): covariance f(q) = sum_p a_p^2 q^p / 2, temperature T,
+ * initial inverse temperature beta0 (0 = random start), memory kernels
+ * K = f''(C) R and D = f'(C), forcing F_C = beta0 f'(C(t,0)) C(t',0),
+ * Lagrange multiplier mu(t) and energy E(t).
+ *
+ * Two discretisations:
+ *  - DMFE_UNIFORM: equidistant grid in t and t' (the O(N^3) baseline of
+ *    Sec. 2.3), classical RK4 with trapezoid history integrals;
+ *  - DMFE_ADAPTIVE: the paper's method (Sec. 3): fixed grid in theta = t'/t
+ *    (eq. theta, alpha = 0), s-point index-Lagrange interpolation in theta and
+ *    cubic Hermite interpolation in t (Sec. 3.3), quadrature sums of eq. (int)
+ *    with quintic-spline weights (Sec. 3.4), Dormand-Prince 5(4) then
+ *    SSPRK(10,4) with the 1-norm error control of Sec. 3.5, and
+ *    sparsification of the stored history (Sec. 3.6).
+ *
+ * Conventions for every entry point:
+ *  - return value: DMFE_OK (0), DMFE_DONE (1, t reached t_max) or a negative
+ *    error code; no C++ exception crosses this boundary;
+ *  - all floating point is IEEE double unless stated;
+ *  - "device" pointers are HIP device addresses on the handle's device;
+ *    "host" pointers are ordinary process memory;
+ *  - work is ordered on the handle's stream; calls that return data to the
+ *    host synchronise that stream before returning;
+ *  - one handle must not be used by two host threads at the same time.
+ */
+#ifndef DMFE_H
+#define DMFE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t dmfe_status;
+
+/* Opaque solver handle. */
+typedef struct dmfe_handle dmfe_handle;
+
+enum {
+    DMFE_OK = 0,
+    DMFE_DONE = 1,                /* t >= t_max after the call */
+    DMFE_ERR_INVALID = -1,        /* bad parameters or arguments */
+    DMFE_ERR_NOMEM = -2,          /* device or host allocation failed, or workspace too small */
+    DMFE_ERR_CAPACITY = -3,       /* history full (M = M_cap) and a sparsification pass freed nothing */
+    DMFE_ERR_STEP_UNDERFLOW = -4, /* the step size fell below dt_min (Appendix B) */
+    DMFE_ERR_NONFINITE = -5,      /* the RK error estimate is NaN or Inf */
+    DMFE_ERR_DEVICE = -6,         /* a HIP call failed; dmfe_last_error() has the text */
+    DMFE_ERR_UNSUPPORTED = -7,    /* valid but not implemented here (e.g. grid_alpha != 0) */
+    DMFE_ERR_BUFFER = -8          /* destination buffer too small; needed_bytes says how much */
+};
+
+enum { DMFE_UNIFORM = 0, DMFE_ADAPTIVE = 1 };
+enum { DMFE_FP64 = 0, DMFE_FP32_COMP = 1 };
+enum { DMFE_SCHEME_DP5 = 0, DMFE_SCHEME_SSPRK104 = 1 };
+enum { DMFE_MAX_TERMS = 8, DMFE_MAX_P = 16 };
+
+/*
+ * Problem statement (Sec. 2.1, 3.2, 3.5, Appendix B).
+ *   n_terms, p[], a2[]  f(q) = sum_k a2[k] q^p[k] / 2, 2 <= p[k] <= DMFE_MAX_P, a2[k] >= 0
+ *   T, beta0            bath temperature, inverse temperature of the initial state
+ *   t_max               largest simulated time; sets gamma = -W_{-1}(-1/t_max) (needs t_max > e)
+ *   mode                DMFE_UNIFORM or DMFE_ADAPTIVE
+ *   precision           DMFE_FP64 (only value accepted by DMFE_UNIFORM) or DMFE_FP32_COMP
+ * uniform mode:
+ *   h, N                step and number of steps (t_max is ignored)
+ * adaptive mode:
+ *   L                   theta-grid length (2s <= L <= 16384)
+ *   M_cap               history capacity in slices (16 <= M_cap <= 16384; 0 means L)
+ *   eps                 tolerance on the 1-norm RK error (Sec. 3.5); sparsification drops
+ *                       a slice whose residual is below eps/10 (Sec. 3.6)
+ *   dt0, dt_min         first step and smallest allowed step
+ *   s                   theta stencil size (4 <= s <= 12; 0 means 10)
+ *   auto_passes         sparsification passes run when M reaches M_cap (0 means 1)
+ *   grid_alpha, grid_delta  flattening parameters of eq. (theta); only alpha = 0 is supported
+ *   scheme_policy       0: DP5 until its stability boundary, then SSPRK(10,4) (default);
+ *                       1: SSPRK(10,4) from the start; 2: DP5 only
+ */
+typedef struct dmfe_params {
+    int32_t n_terms;
+    int32_t p[DMFE_MAX_TERMS];
+    double a2[DMFE_MAX_TERMS];
+    double T;
+    double beta0;
+    double t_max;
+    int32_t mode;
+    int32_t precision;
+    double h;
+    int64_t N;
+    int32_t L;
+    int32_t M_cap;
+    double eps;
+    double dt0;
+    double dt_min;
+    int32_t s;
+    int32_t auto_passes;
+    double grid_alpha;
+    double grid_delta;
+    int32_t scheme_policy;
+    int32_t reserved0;
+} dmfe_params;
+
+/*
+ * Device resources.  `stream` is a hipStream_t (NULL: the null stream).
+ * `workspace`, if not NULL, is caller-owned device memory of at least
+ * dmfe_footprint() bytes that the handle uses instead of allocating; the
+ * handle never frees it and the caller keeps it alive until dmfe_destroy().
+ */
+typedef struct dmfe_resources {
+    int32_t device;
+    int32_t reserved0;
+    void *stream;
+    void *workspace;
+    size_t workspace_bytes;
+} dmfe_resources;
+
+/* Counters and state after dmfe_step / dmfe_get_info. */
+typedef struct dmfe_step_info {
+    int64_t accepted;       /* accepted steps since create */
+    int64_t rejected;       /* rejected steps (each one reverts, Sec. 3.5) */
+    int64_t reverts;        /* slices dropped by reverts */
+    int64_t sparsify_calls; /* sparsification passes run */
+    int64_t removed;        /* slices removed by sparsification */
+    int64_t rhs_evals;      /* right-hand-side evaluations (stages) */
+    int64_t M;              /* stored slices (uniform mode: stored rows) */
+    int32_t scheme;         /* DMFE_SCHEME_* in use */
+    int32_t reserved0;
+    double t;               /* current time */
+    double dt;              /* next step size */
+    double eps_rk;          /* error estimate of the last step */
+} dmfe_step_info;
+
+/* Fields for dmfe_read. */
+typedef enum dmfe_field {
+    DMFE_F_T_GRID = 0,  /* t_n of stored slices, [count]                                  */
+    DMFE_F_THETA = 1,   /* theta_i, [L] (first/count index the grid)                      */
+    DMFE_F_THETA_C = 2, /* 1 - theta_i evaluated without cancellation, [L]                */
+    DMFE_F_NU = 3,      /* quadrature weights nu_i, [L]                                   */
+    DMFE_F_C = 4,       /* C(t_n, theta_i t_n), [count][L]; uniform: packed rows n, C[n][0..n] */
+    DMFE_F_R = 5,       /* R(t_n, theta_i t_n), [count][L]; uniform: packed rows           */
+    DMFE_F_DC = 6,      /* d/dt C(t, theta_i t) at t_n (adaptive only), [count][L]        */
+    DMFE_F_DR = 7,      /* d/dt R(t, theta_i t) at t_n (adaptive only), [count][L]        */
+    DMFE_F_ENERGY = 8,  /* E(t_n), [count]                                                 */
+    DMFE_F_MU = 9       /* mu(t_n), [count]                                                */
+} dmfe_field;
+
+/* Bytes of device memory the handle needs for these parameters (host only, no device call). */
+dmfe_status dmfe_footprint(const dmfe_params *params, size_t *bytes);
+
+/*
+ * Create a solver: validates params, computes the run-constant grid data on the
+ * host (gamma, theta, nu), takes or allocates device memory and sets the
+ * initial slice C(0,0) = R(0,0^-) = 1 (Sec. 2.2).  *out receives the handle.
+ */
+dmfe_status dmfe_create(const dmfe_params *params, const dmfe_resources *res, dmfe_handle **out);
+
+/*
+ * Advance until t >= t_target (uniform mode: until n h >= t_target) or until
+ * max_steps steps (accepted + rejected) were taken.  Sparsification runs
+ * automatically when the history reaches M_cap.  info may be NULL.
+ * Returns DMFE_DONE once t >= t_max (adaptive) or n = N (uniform).
+ */
+dmfe_status dmfe_step(dmfe_handle *h, double t_target, int64_t max_steps, dmfe_step_info *info);
+
+/*
+ * Run `passes` sparsification passes over the stored history (Sec. 3.6):
+ * for each candidate slice n = 1..M-12 (the first slice and the revert window
+ * of the last eleven are kept) the residual eps_n = sum_i |Delta^C| + |Delta^R|
+ * of the Hermite integrals over [t_{n-1}, t_{n+1}] with and without n is
+ * formed on the device; a greedy sweep drops n when eps_n < eps/10 and then
+ * skips n+1.  *removed (may be NULL) receives the number of slices dropped.
+ */
+dmfe_status dmfe_sparsify(dmfe_handle *h, int32_t passes, int64_t *removed);
+
+/*
+ * Copy `count` entries starting at `first` of a field into dst (device memory
+ * if dst_on_device, else host).  With dst == NULL only *needed_bytes is set.
+ * Returns DMFE_ERR_BUFFER if dst_bytes is too small, DMFE_ERR_INVALID if the
+ * range is outside the stored data.
+ */
+dmfe_status dmfe_read(dmfe_handle *h, int32_t field, int64_t first, int64_t count, void *dst, size_t dst_bytes,
+                      int32_t dst_on_device, size_t *needed_bytes);
+
+/* Current counters and state (no device synchronisation beyond the stream's). */
+dmfe_status dmfe_get_info(dmfe_handle *h, dmfe_step_info *info);
+
+/*
+ * Replace the stored history (adaptive mode).  t_hist[M] strictly increasing
+ * with t_hist[0] = 0; C, R, dC, dR are [M][L] row-major (host or device as
+ * src_on_device says); slices 0..nb-1 carry valid d/dt (nb = M or M-1).  The
+ * state becomes slice M-1.  dt and scheme set the controller (dt <= 0 keeps
+ * the current one).  Used to resume a run and to feed synthetic histories.
+ */
+dmfe_status dmfe_set_history(dmfe_handle *h, int64_t M, int64_t nb, const double *t_hist, const double *C,
+                             const double *R, const double *dC, const double *dR, int32_t src_on_device,
+                             double dt, int32_t scheme);
+
+/*
+ * One evaluation of the right-hand side on the theta grid (the hot path,
+ * Sec. 3.3-3.4): d/dt C(t, theta_j t) and d/dt R(t, theta_j t) for all j at
+ * stage time t >= t_{nb-1}, for the stage slice (yC, yR) [L] on the stored
+ * history with slices 0..nb-1 carrying valid d/dt.  yC, yR, outC, outR are
+ * device pointers.  Row L-1 (the diagonal) is pinned: outC[L-1] = outR[L-1] = 0
+ * and the values computed there are returned in diag[2] (host, may be NULL).
+ * mu (host, may be NULL) receives mu(t).  The history is not modified.
+ */
+dmfe_status dmfe_rhs(dmfe_handle *h, double t, const double *yC, const double *yR, int64_t nb, double *outC,
+                     double *outR, double *mu, double *diag);
+
+void dmfe_destroy(dmfe_handle *h);
+
+/* Static text for a status code. */
+const char *dmfe_status_string(dmfe_status s);
+
+/* Text of the last HIP failure seen by any handle in this thread ("" if none). */
+const char *dmfe_last_error(void);
+
+/* ---------------------------------------------------------------- host-only helpers
+ * These run on the host without touching a device; they expose the
+ * run-constant precompute and the scalar control logic the solver uses. */
+
+/*
+ * theta_i, 1 - theta_i and nu_i for the grid of these params (adaptive mode):
+ * eq. (theta) at alpha = 0 with gamma = -W_{-1}(-1/t_max), and the integrals
+ * of the not-a-knot quintic interpolating spline (Sec. 3.4).  Arrays of L
+ * doubles (host).  *gamma (may be NULL) receives gamma.
+ */
+dmfe_status dmfe_grid(const dmfe_params *params, double *theta, double *theta_c, double *nu, double *gamma);
+
+/*
+ * Controller of Sec. 3.5 as a pure function of the last error estimate.
+ * In: eps_rk, and *st (dt, scheme, M = stored slices before the step).
+ * Out: *accepted (1/0), *n_revert (slices to drop when rejected) and the
+ * updated *st (dt, scheme).  Rules: reject if eps_rk > 2 eps (revert
+ * min(10, M-1) slices, halve dt); else accept and scale dt by 0.9 if
+ * eps_rk > eps, by 1.01 if eps_rk < eps/2; DP5 switches to SSPRK(10,4) once
+ * dt * 4 sqrt(f''(1)) reaches its real-axis stability limit, halving dt;
+ * under SSPRK(10,4) dt is capped at its own real-axis limit.
+ */
+typedef struct dmfe_control {
+    double eps;
+    double dt;
+    double dt_min;
+    double rho; /* 4 sqrt(f''(1)), the spectral bound of Sec. 3.5 */
+    int64_t M;
+    int32_t scheme;
+    int32_t policy;
+} dmfe_control;
+
+dmfe_status dmfe_control_update(dmfe_control *st, double eps_rk, int32_t *accepted, int32_t *n_revert);
+
+/*
+ * Greedy selection of one sparsification pass (Sec. 3.6) on host residuals:
+ * candidates n = 1..last; drop[n] = 1 when eps_n[n] < thr and n-1 was not
+ * dropped.  drop has M entries (host).  *removed receives the count.
+ */
+dmfe_status dmfe_sparsify_select(const double *eps_n, int64_t M, int64_t last, double thr, uint8_t *drop,
+                                 int64_t *removed);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DMFE_H */

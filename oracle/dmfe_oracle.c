@@ -89,17 +89,22 @@ static void uni_rhs(const or_model *m, int n, double h, double delta,
                     const double *Ct, const double *Rt,
                     const double *c, const double *r, double *dc, double *dr) {
     double *W = (double *)malloc(sizeof(double) * (n + 1));
-    for (int q = 0; q <= n; ++q) W[q] = trap_w(q, 0, n, h);
+    double *g1 = (double *)malloc(sizeof(double) * (n + 1)); /* f'(c_q)  */
+    double *g2 = (double *)malloc(sizeof(double) * (n + 1)); /* f''(c_q) */
+    for (int q = 0; q <= n; ++q) {
+        W[q] = trap_w(q, 0, n, h);
+        g1[q] = or_f1(m, c[q]);
+        g2[q] = or_f2(m, c[q]);
+    }
     W[n] += 0.5 * delta;
     const double Ws = 0.5 * delta;
     const double f1one = or_f1(m, 1.0), f2one = or_f2(m, 1.0);
 
     /* mu(t) = T + int_0^t [K C + D R](t,s) ds + F_C(t,t) */
     double mu = m->T;
-    for (int q = 0; q <= n; ++q)
-        mu += W[q] * (or_f2(m, c[q]) * r[q] * c[q] + or_f1(m, c[q]) * r[q]);
+    for (int q = 0; q <= n; ++q) mu += W[q] * (g2[q] * r[q] * c[q] + g1[q] * r[q]);
     mu += Ws * (f2one + f1one);
-    mu += m->beta0 * or_f1(m, c[0]) * c[0];
+    mu += m->beta0 * g1[0] * c[0];
 
 #pragma omp parallel for schedule(dynamic, 8)
     for (int k = 0; k <= n; ++k) {
@@ -107,23 +112,25 @@ static void uni_rhs(const or_model *m, int n, double h, double delta,
         double A = 0.0;
         for (int q = 0; q <= n; ++q) {
             double Cqk = (q >= k) ? Ct[tri(q, k)] : Ct[tri(k, q)];
-            A += W[q] * or_f2(m, c[q]) * r[q] * Cqk;
+            A += W[q] * g2[q] * r[q] * Cqk;
         }
         A += Ws * f2one * c[k];
         /* int_0^{t_k} D(t,s) R(t_k,s) ds */
         double B = 0.0;
-        for (int q = 0; q <= k; ++q) B += trap_w(q, 0, k, h) * or_f1(m, c[q]) * Rt[tri(k, q)];
+        for (int q = 0; q <= k; ++q) B += trap_w(q, 0, k, h) * g1[q] * Rt[tri(k, q)];
         /* int_{t_k}^t K(t,s) R(s,t_k) ds */
         double Q = 0.0;
         for (int q = k; q <= n; ++q) {
             double w = trap_w(q, k, n, h) + (q == n ? 0.5 * delta : 0.0);
-            Q += w * or_f2(m, c[q]) * r[q] * Rt[tri(q, k)];
+            Q += w * g2[q] * r[q] * Rt[tri(q, k)];
         }
         Q += Ws * f2one * r[k];
-        dc[k] = -mu * c[k] + A + B + m->beta0 * or_f1(m, c[0]) * Ct[tri(k, 0)];
+        dc[k] = -mu * c[k] + A + B + m->beta0 * g1[0] * Ct[tri(k, 0)];
         dr[k] = -mu * r[k] + Q;
     }
     free(W);
+    free(g1);
+    free(g2);
 }
 
 /* E(t_n) = -int_0^{t_n} f'(C(t_n,s)) R(t_n,s) ds - beta0 f(C(t_n,0))  (Sec. 2.1) */

@@ -102,11 +102,18 @@ def lib():
         _lib.or_adaptive_run.restype = i
         _lib.or_adaptive_run.argtypes = [ctypes.POINTER(Model), ctypes.POINTER(Grid), ctypes.POINTER(Adapt),
                                          ctypes.POINTER(State), d, ctypes.c_int64]
+        _lib.or_num_threads.restype = i
+        _lib.or_num_threads.argtypes = []
         _lib.or_sizeof.restype = i
         _lib.or_sizeof.argtypes = [i]
         for k, cls in enumerate([Model, Grid, Hist, Tableau, Adapt, State]):
             assert _lib.or_sizeof(k) == ctypes.sizeof(cls), cls.__name__
     return _lib
+
+
+def num_threads() -> int:
+    """OpenMP threads the oracle's parallel loops use."""
+    return lib().or_num_threads()
 
 
 def _p(a: np.ndarray):

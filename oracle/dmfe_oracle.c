@@ -31,6 +31,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define OR_MAX_TERMS 8
 
@@ -648,6 +651,15 @@ int or_adaptive_run(const or_model *m, const or_grid *g, const or_adapt *ad, or_
     free(y0); free(ys); free(k);
     if (status == OR_OK && s->t[s->M - 1] >= t_target) status = OR_DONE;
     return status;
+}
+
+/* threads the OpenMP loops of this file use */
+int or_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
 
 /* struct sizes, so the Python side can check its ctypes mirrors */

@@ -1,0 +1,282 @@
+#!/usr/bin/env python3
+"""RK steps/s of the MI355X DMFE solver at theta-grid length L = 4096.
+
+Workload: the mixed spherical 3+4 model (a_3^2 = a_4^2 = 1/2) at T = 0.55 with
+t_max = 1e7 (gamma = 19.066), L = 4096, history capacity 4096 slices,
+tolerance 1e-8, DP5 then SSPRK(10,4), automatic sparsification.  Inputs are
+the model parameters: the history is produced by the solver itself.
+
+Phases: (1) untimed fill from t = 0 until the history first reaches its
+capacity and an automatic sparsification pass has run (the steady state of
+the method), (2) W untimed warm-up steps, (3) exactly K timed steps between
+device synchronisations.  Per-kernel durations are HIP events recorded by the
+library on its own stream during (3).
+
+One JSON line is printed on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+METRIC = "RK steps/s at grid L=4096 (FP64 vs FP32-comp); sweep solves/s + p99 latency"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload_params(pk, precision):
+    return pk.make_params({3: 0.5, 4: 0.5}, 0.55, t_max=1e7, L=4096, M_cap=4096, eps=1e-8, dt0=1e-3,
+                          dt_min=1e-12, precision=precision)
+
+
+def hist_integral_bytes(L: int, slices: float) -> float:
+    """Algorithmic bytes of one history-integral launch: every stored point of
+    the slices with a derivative (4 doubles) once, the stage slice and the
+    output (2 doubles each per grid point) and theta, 1-theta, nu."""
+    return slices * L * 32.0 + L * (16.0 + 16.0 + 24.0)
+
+
+def cpu_baseline(L: int, M: int, evals_per_step: float, budget_s: float = 20.0):
+    """The oracle's right-hand side on a synthetic history of the same shape,
+    timed on a sample of rows and scaled to one RK step."""
+    import numpy as np
+
+    import oracle
+
+    ts = oracle.ThetaSetup(L, 1e7)
+    m = oracle.make_model({3: 0.5, 4: 0.5}, T=0.55)
+    rng = np.random.default_rng(20260406)
+    times = np.concatenate([[0.0], np.geomspace(1e-2, 3000.0, M - 1)])
+    k = 0.5 + 0.2 * rng.random()
+    C = np.exp(-k * np.outer(times, ts.thc))
+    R = np.exp(-1.3 * k * np.outer(times, ts.thc))
+    dC = -k * ts.thc * C
+    dR = -1.3 * k * ts.thc * R
+    t = 3000.0 * 1.0005
+    yC = np.exp(-k * t * ts.thc)
+    yR = np.exp(-1.3 * k * t * ts.thc)
+    threads = oracle.num_threads()
+    done, elapsed, nrows = 0, 0.0, 16
+    order = rng.permutation(L)
+    while done < L and elapsed < budget_s:
+        rows = order[done:done + nrows]
+        t0 = time.perf_counter()
+        oracle.theta_rhs(m, ts, times, C, R, dC, dR, M, t, yC, yR, rows=rows)
+        elapsed += time.perf_counter() - t0
+        done += rows.size
+        nrows *= 2
+        log(f"cpu baseline: {done} rows in {elapsed:.1f} s")
+    per_eval = elapsed / done * L
+    return {"value": 1.0 / (per_eval * evals_per_step), "unit": "steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{done} of {L} rows of one right-hand-side evaluation at L={L}, M={M} "
+                      f"(synthetic smooth history), scaled to {evals_per_step:.2f} evaluations per step"}
+
+
+def sweep_requests(pk, n: int, seed: int, precision: int, tmax_range=(10.0, 100.0)):
+    """Parameter-sweep requests: T ~ U[0.4, 1.2], (a2^2, a3^2, a4^2) ~ Dirichlet(1,1,1),
+    t_max log-uniform on tmax_range, L uniform on {512, 1024, 2048, 4096}, history cap L."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for _ in range(n):
+        a2 = rng.dirichlet([1.0, 1.0, 1.0])
+        L = int(rng.choice([512, 1024, 2048, 4096]))
+        tmax = float(np.exp(rng.uniform(np.log(tmax_range[0]), np.log(tmax_range[1]))))
+        reqs.append(pk.make_params({2: a2[0], 3: a2[1], 4: a2[2]}, float(rng.uniform(0.4, 1.2)), t_max=tmax, L=L,
+                                   M_cap=L, eps=1e-6, dt0=1e-3, dt_min=1e-12, precision=precision))
+    return reqs
+
+
+def serving_sweep(pk, n: int = 24, seed: int = 20260406):
+    """Solves/s and time-to-solution of the serving pool (FP32-comp histories) on a
+    scaled sweep, next to the same requests solved one after another in FP64."""
+    import numpy as np
+    import torch
+
+    out = {}
+    # (a) the same requests as plain FP64 solves, one after another
+    t0 = time.perf_counter()
+    for p in sweep_requests(pk, n, seed, pk.FP64):
+        s = pk.Solver(p)
+        s.step(float("inf"))
+        s.close()
+    torch.cuda.synchronize()
+    t_seq64 = time.perf_counter() - t0
+    out["sequential_fp64_solves_per_s"] = n / t_seq64
+    log(f"serving: {n} sequential FP64 solves in {t_seq64:.1f} s")
+    reqs = sweep_requests(pk, n, seed, pk.FP32_COMP)
+    arena = int(0.5 * torch.cuda.mem_get_info()[0])
+    # (b) closed batch: all requests at once -> capacity
+    pool = pk.Pool(arena, max_instances=256)
+    t0 = time.perf_counter()
+    ids = [pool.submit(p) for p in reqs]
+    done = 0
+    while done < n:
+        pool.run(50)
+        for rid in pool.poll():
+            pool.release(rid)
+            done += 1
+    t_batch = time.perf_counter() - t0
+    cap = n / t_batch
+    out["batch_solves_per_s"] = cap
+    log(f"serving: closed batch of {n} in {t_batch:.1f} s ({cap:.2f} solves/s)")
+    pool.close()
+    # (c) Poisson arrivals at 0.8 x capacity: time to solution
+    rng = np.random.default_rng(seed + 1)
+    arrivals = np.cumsum(rng.exponential(1.0 / (0.8 * cap), n))
+    pool = pk.Pool(arena, max_instances=256)
+    t0 = time.perf_counter()
+    nxt, tts, status = 0, [], []
+    while len(tts) < n:
+        now = time.perf_counter() - t0
+        while nxt < n and arrivals[nxt] <= now:
+            pool.submit(reqs[nxt])
+            nxt += 1
+        st = pool.run(20)
+        for rid in pool.poll():
+            _, tm = pool.result(rid)
+            tts.append(tm.total_s)
+            status.append(tm.status)
+            pool.release(rid)
+        if st.running == 0 and st.queued == 0 and nxt < n:
+            time.sleep(max(0.0, min(arrivals[nxt] - (time.perf_counter() - t0), 0.05)))
+    t_open = time.perf_counter() - t0
+    pool.close()
+    tts = np.array(tts)
+    out.update({
+        "poisson_solves_per_s": n / t_open,
+        "arrival_rate_per_s": 0.8 * cap,
+        "p50_time_to_solution_s": float(np.percentile(tts, 50)),
+        "p99_time_to_solution_s": float(np.percentile(tts, 99)),
+        "all_reached_t_max": bool(all(x == pk.DONE for x in status)),
+        "speedup_vs_sequential_fp64": cap / out["sequential_fp64_solves_per_s"],
+        "sweep": f"{n} requests: T~U[0.4,1.2], (a2^2,a3^2,a4^2)~Dirichlet(1,1,1), t_max~logU[10,100], "
+                 f"L~U{{512,1024,2048,4096}}, history cap L, eps=1e-6, FP32-comp histories, seed {seed}",
+    })
+    log(f"serving: Poisson run {t_open:.1f} s, p50 {out['p50_time_to_solution_s']:.2f} s, "
+        f"p99 {out['p99_time_to_solution_s']:.2f} s")
+    return out
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--precision", choices=["fp64", "fp32c"], default="fp64")
+    ap.add_argument("--fill-seconds", type=float, default=150.0, help="time budget of the untimed fill phase")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serving", type=int, default=24, help="requests in the serving sweep (0: skip)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the solver has no multi-GPU path; "
+              f"independent solves shard trivially across GPUs and are not benchmarked here.", file=sys.stderr)
+        return 2
+
+    import torch
+
+    import paper_2604_06309_amd as pk
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    prec = pk.FP64 if args.precision == "fp64" else pk.FP32_COMP
+    params = workload_params(pk, prec)
+    L = params.L
+    s = pk.Solver(params)
+
+    # (1) fill until the history has reached its capacity and been sparsified once
+    t_fill = time.perf_counter()
+    steady = False
+    while time.perf_counter() - t_fill < args.fill_seconds:
+        _, info = s.step(float("inf"), 250)
+        log(f"fill: steps={info.accepted + info.rejected} M={info.M} t={info.t:.5g} dt={info.dt:.3g} "
+            f"scheme={info.scheme} sparsify={info.sparsify_calls} ({time.perf_counter() - t_fill:.1f} s)")
+        if info.sparsify_calls >= 1:
+            steady = True
+            break
+    # (2) warm-up
+    s.step(float("inf"), args.warmup)
+    # (3) timed window
+    i0 = s.info()
+    s.timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, i1 = s.step(float("inf"), args.steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    n_hi, ms_hi, slices_hi = s.timing_read(pk.K_HIST_INTEGRAL)
+    n_sp, ms_sp, _ = s.timing_read(pk.K_SPARSIFY)
+    n_pr, ms_pr, _ = s.timing_read(pk.K_STAGE_PREP)
+    n_rk, ms_rk, _ = s.timing_read(pk.K_RK)
+    s.timing(False)
+    steps = (i1.accepted + i1.rejected) - (i0.accepted + i0.rejected)
+    assert steps == args.steps, (steps, args.steps)
+    evals = i1.rhs_evals - i0.rhs_evals
+    value = steps / elapsed
+    avg_ms = ms_hi / n_hi
+    avg_slices = slices_hi / n_hi
+    achieved = hist_integral_bytes(L, avg_slices) / (avg_ms * 1e-3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == pk.FP64 else "f32+f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "mixed spherical 3+4 (a3^2=a4^2=1/2), T=0.55, t_max=1e7, theta grid L=4096, "
+                        "history cap 4096, eps=1e-8, DP5 then SSPRK(10,4), automatic sparsification",
+            "precision": args.precision,
+            "L": L,
+            "M_cap": params.M_cap,
+            "steady_state": steady,
+            "M_window": [int(i0.M), int(i1.M)],
+            "mean_slices_per_stage": avg_slices,
+            "t_window": [i0.t, i1.t],
+            "dt_end": i1.dt,
+            "scheme_end": "SSPRK(10,4)" if i1.scheme == pk.SCHEME_SSPRK104 else "DP5",
+            "rhs_evals_per_step": evals / steps,
+            "sparsify_passes_in_window": int(i1.sparsify_calls - i0.sparsify_calls),
+            "kernel_ms_per_step": {
+                "hist_integral": ms_hi / steps, "stage_prep": ms_pr / steps, "rk": ms_rk / steps,
+                "sparsify_residual": ms_sp / steps},
+        },
+        "roofline": {
+            "kernel": "hist_integral",
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": achieved / PEAK_HBM_GBS,
+            "traffic": None,
+            "avg_launch_us": avg_ms * 1e3,
+            "launches": n_hi,
+            "algorithmic_bytes_per_launch": hist_integral_bytes(L, avg_slices),
+        },
+    }
+    s.close()
+    if args.serving > 0:
+        out["serving"] = serving_sweep(pk, args.serving)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(L, int(round(avg_slices)) if avg_slices > 16 else L, evals / steps)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

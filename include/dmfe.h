@@ -161,8 +161,8 @@ dmfe_status dmfe_footprint(const dmfe_params *params, size_t *bytes);
 dmfe_status dmfe_create(const dmfe_params *params, const dmfe_resources *res, dmfe_handle **out);
 
 /*
- * Advance until t >= t_target (uniform mode: until n h >= t_target) or until
- * max_steps steps (accepted + rejected) were taken.  Sparsification runs
+ * Advance until t >= min(t_target, t_max) (uniform mode: until n h >= t_target
+ * or n = N) or until max_steps steps (accepted + rejected) were taken.  Sparsification runs
  * automatically when the history reaches M_cap.  info may be NULL.
  * Returns DMFE_DONE once t >= t_max (adaptive) or n = N (uniform).
  */
@@ -215,11 +215,82 @@ dmfe_status dmfe_rhs(dmfe_handle *h, double t, const double *yC, const double *y
 
 void dmfe_destroy(dmfe_handle *h);
 
+/*
+ * Per-kernel timing with HIP events recorded on the handle's stream around
+ * every launch of the timed kernels (enable = 1 starts and zeroes the
+ * counters, 0 stops).  Kernel ids: DMFE_K_HIST_INTEGRAL (the history-integral
+ * kernel), DMFE_K_STAGE_PREP (mu, E), DMFE_K_RK (stage combination and error
+ * norm), DMFE_K_SPARSIFY (sparsification residual).  dmfe_timing_read returns
+ * the number of timed launches, their summed duration in milliseconds, and
+ * the summed number of stored slices the launches read (history-integral
+ * kernel: slices with a stored derivative; others: 0).
+ */
+enum { DMFE_K_HIST_INTEGRAL = 0, DMFE_K_STAGE_PREP = 1, DMFE_K_RK = 2, DMFE_K_SPARSIFY = 3, DMFE_K_COUNT = 4 };
+dmfe_status dmfe_timing(dmfe_handle *h, int32_t enable);
+dmfe_status dmfe_timing_read(dmfe_handle *h, int32_t kernel, int64_t *launches, double *total_ms,
+                             int64_t *slices_read);
+
 /* Static text for a status code. */
 const char *dmfe_status_string(dmfe_status s);
 
 /* Text of the last HIP failure seen by any handle in this thread ("" if none). */
 const char *dmfe_last_error(void);
+
+/* ---------------------------------------------------------------- serving pool
+ * Many solves (a parameter sweep: different T, a_p, t_max, L) stepped
+ * together on one device.  Requests queue on submit and are admitted while a
+ * slot is free and their footprint (dmfe_footprint) fits in the pool's arena;
+ * admitted solves keep their history resident and advance together, one RK
+ * stage per tick, each phase of a tick being one batched launch over all of
+ * them (uneven L and M per solve).  Finished solves keep their memory until
+ * dmfe_pool_release, so results can be read; released memory admits queued
+ * requests.  All solves of a pool use the same history precision and s = 10.
+ */
+typedef struct dmfe_pool dmfe_pool;
+
+typedef struct dmfe_pool_params {
+    int32_t max_instances; /* admitted solves at most (1..4096) */
+    int32_t reserved0;
+    size_t max_bytes;      /* arena bytes used, 0: all of res->workspace_bytes */
+} dmfe_pool_params;
+
+typedef struct dmfe_pool_stats {
+    int32_t running;             /* admitted and not finished */
+    int32_t queued;              /* submitted, not yet admitted */
+    int32_t finished_unreleased; /* finished, memory still held */
+    int32_t reserved0;
+    int64_t ticks;               /* stage ticks run so far */
+    size_t bytes_free;
+    size_t bytes_total;
+} dmfe_pool_stats;
+
+typedef struct dmfe_pool_times {
+    int32_t status;   /* DMFE_DONE when the solve reached its t_max, else its error code */
+    int32_t done;     /* 1 once finished */
+    double queue_s;   /* submit -> admit */
+    double service_s; /* admit -> done (or now) */
+    double total_s;   /* submit -> done (or now): time to solution */
+} dmfe_pool_times;
+
+/* res->workspace (device memory, caller-owned, res->workspace_bytes bytes) is the
+ * arena; res->stream orders all work of the pool. */
+dmfe_status dmfe_pool_create(const dmfe_pool_params *pp, const dmfe_resources *res, dmfe_pool **out);
+/* Queue a solve (adaptive mode); *request_id identifies it.  DMFE_ERR_NOMEM if it
+ * can never fit, DMFE_ERR_UNSUPPORTED for s != 10 or a precision other than the pool's. */
+dmfe_status dmfe_pool_submit(dmfe_pool *pool, const dmfe_params *params, uint64_t *request_id);
+/* Run up to max_ticks stage ticks (returns early when nothing is running and
+ * nothing can be admitted); stats may be NULL. */
+dmfe_status dmfe_pool_run(dmfe_pool *pool, int64_t max_ticks, dmfe_pool_stats *stats);
+/* Ids of solves finished since the last poll (up to cap). */
+dmfe_status dmfe_pool_poll(dmfe_pool *pool, uint64_t *done_ids, int32_t cap, int32_t *n_done);
+/* State and timings of an admitted or finished solve (info, times may be NULL). */
+dmfe_status dmfe_pool_result(dmfe_pool *pool, uint64_t request_id, dmfe_step_info *info, dmfe_pool_times *times);
+/* dmfe_read on an admitted or finished solve. */
+dmfe_status dmfe_pool_read(dmfe_pool *pool, uint64_t request_id, int32_t field, int64_t first, int64_t count, void *dst,
+                           size_t dst_bytes, int32_t dst_on_device, size_t *needed_bytes);
+/* Free a finished solve's memory. */
+dmfe_status dmfe_pool_release(dmfe_pool *pool, uint64_t request_id);
+void dmfe_pool_destroy(dmfe_pool *pool);
 
 /* ---------------------------------------------------------------- host-only helpers
  * These run on the host without touching a device; they expose the

@@ -30,6 +30,7 @@ UNIFORM, ADAPTIVE = 0, 1
 FP64, FP32_COMP = 0, 1
 SCHEME_DP5, SCHEME_SSPRK104 = 0, 1
 F_T_GRID, F_THETA, F_THETA_C, F_NU, F_C, F_R, F_DC, F_DR, F_ENERGY, F_MU = range(10)
+K_HIST_INTEGRAL, K_STAGE_PREP, K_RK, K_SPARSIFY = range(4)
 
 
 class dmfe_params(ctypes.Structure):
@@ -63,6 +64,21 @@ class dmfe_control(ctypes.Structure):
                 ("policy", ctypes.c_int32)]
 
 
+class dmfe_pool_params(ctypes.Structure):
+    _fields_ = [("max_instances", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("max_bytes", ctypes.c_size_t)]
+
+
+class dmfe_pool_stats(ctypes.Structure):
+    _fields_ = [("running", ctypes.c_int32), ("queued", ctypes.c_int32), ("finished_unreleased", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32), ("ticks", ctypes.c_int64), ("bytes_free", ctypes.c_size_t),
+                ("bytes_total", ctypes.c_size_t)]
+
+
+class dmfe_pool_times(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("done", ctypes.c_int32), ("queue_s", ctypes.c_double),
+                ("service_s", ctypes.c_double), ("total_s", ctypes.c_double)]
+
+
 _lib = None
 
 # exported symbol -> (restype, argtypes)
@@ -82,6 +98,18 @@ SIGNATURES = {
     "dmfe_grid": (_i32, [ctypes.POINTER(dmfe_params), _vp, _vp, _vp, _vp]),
     "dmfe_control_update": (_i32, [ctypes.POINTER(dmfe_control), _d, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "dmfe_sparsify_select": (_i32, [_vp, _i64, _i64, _d, _vp, ctypes.POINTER(_i64)]),
+    "dmfe_timing": (_i32, [_vp, _i32]),
+    "dmfe_pool_create": (_i32, [ctypes.POINTER(dmfe_pool_params), ctypes.POINTER(dmfe_resources),
+                                ctypes.POINTER(_vp)]),
+    "dmfe_pool_submit": (_i32, [_vp, ctypes.POINTER(dmfe_params), ctypes.POINTER(ctypes.c_uint64)]),
+    "dmfe_pool_run": (_i32, [_vp, _i64, ctypes.POINTER(dmfe_pool_stats)]),
+    "dmfe_pool_poll": (_i32, [_vp, ctypes.POINTER(ctypes.c_uint64), _i32, ctypes.POINTER(_i32)]),
+    "dmfe_pool_result": (_i32, [_vp, ctypes.c_uint64, ctypes.POINTER(dmfe_step_info),
+                                ctypes.POINTER(dmfe_pool_times)]),
+    "dmfe_pool_read": (_i32, [_vp, ctypes.c_uint64, _i32, _i64, _i64, _vp, _sz, _i32, ctypes.POINTER(_sz)]),
+    "dmfe_pool_release": (_i32, [_vp, ctypes.c_uint64]),
+    "dmfe_pool_destroy": (None, [_vp]),
+    "dmfe_timing_read": (_i32, [_vp, _i32, ctypes.POINTER(_i64), ctypes.POINTER(_d), ctypes.POINTER(_i64)]),
 }
 
 
@@ -211,6 +239,17 @@ def dmfe_rhs(h: int, t: float, yC, yR, nb: int):
     return outC, outR, mu.value, diag
 
 
+def dmfe_timing(h: int, enable: bool) -> None:
+    _check(lib().dmfe_timing(h, int(enable)), "dmfe_timing")
+
+
+def dmfe_timing_read(h: int, kernel: int) -> tuple[int, float, int]:
+    n, ms, sl = ctypes.c_int64(), ctypes.c_double(), ctypes.c_int64()
+    _check(lib().dmfe_timing_read(h, kernel, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(sl)),
+           "dmfe_timing_read")
+    return n.value, ms.value, sl.value
+
+
 def dmfe_destroy(h: int) -> None:
     if h:
         lib().dmfe_destroy(h)
@@ -246,6 +285,111 @@ def dmfe_sparsify_select(eps_n: np.ndarray, last: int, thr: float):
     _check(lib().dmfe_sparsify_select(_ptr(e), e.size, last, thr, _ptr(drop), ctypes.byref(rem)),
            "dmfe_sparsify_select")
     return rem.value, drop.astype(bool)
+
+
+# ----------------------------------------------------------------------------- serving pool
+def dmfe_pool_create(max_instances: int, device: int, stream: int, arena_ptr: int, arena_bytes: int,
+                     max_bytes: int = 0) -> int:
+    pp = dmfe_pool_params()
+    pp.max_instances, pp.max_bytes = max_instances, max_bytes
+    r = dmfe_resources()
+    r.device, r.stream, r.workspace, r.workspace_bytes = device, stream or None, arena_ptr, arena_bytes
+    h = ctypes.c_void_p()
+    _check(lib().dmfe_pool_create(ctypes.byref(pp), ctypes.byref(r), ctypes.byref(h)), "dmfe_pool_create", (OK,))
+    return h.value
+
+
+def dmfe_pool_submit(pool: int, params: dmfe_params) -> int:
+    rid = ctypes.c_uint64()
+    _check(lib().dmfe_pool_submit(pool, ctypes.byref(params), ctypes.byref(rid)), "dmfe_pool_submit", (OK,))
+    return rid.value
+
+
+def dmfe_pool_run(pool: int, max_ticks: int) -> dmfe_pool_stats:
+    st = dmfe_pool_stats()
+    _check(lib().dmfe_pool_run(pool, max_ticks, ctypes.byref(st)), "dmfe_pool_run", (OK,))
+    return st
+
+
+def dmfe_pool_poll(pool: int, cap: int = 4096) -> list[int]:
+    ids = (ctypes.c_uint64 * cap)()
+    n = ctypes.c_int32()
+    _check(lib().dmfe_pool_poll(pool, ids, cap, ctypes.byref(n)), "dmfe_pool_poll", (OK,))
+    return [ids[k] for k in range(n.value)]
+
+
+def dmfe_pool_result(pool: int, rid: int) -> tuple[dmfe_step_info, dmfe_pool_times]:
+    info, tm = dmfe_step_info(), dmfe_pool_times()
+    _check(lib().dmfe_pool_result(pool, rid, ctypes.byref(info), ctypes.byref(tm)), "dmfe_pool_result", (OK,))
+    return info, tm
+
+
+def dmfe_pool_read(pool: int, rid: int, field: int, first: int, count: int, dst: Optional[np.ndarray] = None) -> int:
+    need = ctypes.c_size_t()
+    if dst is None:
+        _check(lib().dmfe_pool_read(pool, rid, field, first, count, None, 0, 0, ctypes.byref(need)), "dmfe_pool_read")
+        return need.value
+    _check(lib().dmfe_pool_read(pool, rid, field, first, count, _ptr(dst), dst.nbytes, 0, ctypes.byref(need)),
+           "dmfe_pool_read")
+    return need.value
+
+
+def dmfe_pool_release(pool: int, rid: int) -> None:
+    _check(lib().dmfe_pool_release(pool, rid), "dmfe_pool_release", (OK,))
+
+
+def dmfe_pool_destroy(pool: int) -> None:
+    if pool:
+        lib().dmfe_pool_destroy(pool)
+
+
+class Pool:
+    """A serving pool over a caller-owned arena (a torch uint8 tensor on the device)."""
+
+    def __init__(self, arena_bytes: int, max_instances: int = 256, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("Pool needs a GPU (HIP device)")
+        dev = torch.cuda.current_device()
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        self.arena = torch.empty(arena_bytes, dtype=torch.uint8, device=f"cuda:{dev}")
+        self.p = dmfe_pool_create(max_instances, dev, self.stream.cuda_stream, self.arena.data_ptr(), arena_bytes)
+
+    def submit(self, params: dmfe_params) -> int:
+        return dmfe_pool_submit(self.p, params)
+
+    def run(self, max_ticks: int = 1 << 40) -> dmfe_pool_stats:
+        return dmfe_pool_run(self.p, max_ticks)
+
+    def poll(self) -> list[int]:
+        return dmfe_pool_poll(self.p)
+
+    def result(self, rid: int):
+        return dmfe_pool_result(self.p, rid)
+
+    def read(self, rid: int, field: int, first: int = 0, count: Optional[int] = None, L: Optional[int] = None):
+        if count is None:
+            count = int(self.result(rid)[0].M) - first
+        need = dmfe_pool_read(self.p, rid, field, first, count)
+        out = np.empty(need // 8)
+        dmfe_pool_read(self.p, rid, field, first, count, out)
+        if L is not None and field in (F_C, F_R, F_DC, F_DR):
+            out = out.reshape(count, L)
+        return out
+
+    def release(self, rid: int) -> None:
+        dmfe_pool_release(self.p, rid)
+
+    def close(self):
+        if getattr(self, "p", None):
+            dmfe_pool_destroy(self.p)
+            self.p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ----------------------------------------------------------------------------- convenience wrapper
@@ -307,3 +451,9 @@ class Solver:
 
     def rhs(self, t: float, yC, yR, nb: int):
         return dmfe_rhs(self.h, t, yC, yR, nb)
+
+    def timing(self, enable: bool) -> None:
+        dmfe_timing(self.h, enable)
+
+    def timing_read(self, kernel: int) -> tuple[int, float, int]:
+        return dmfe_timing_read(self.h, kernel)

@@ -11,31 +11,20 @@
 #include <string>
 #include <vector>
 
-#include "dmfe_internal.h"
+#include "handle.h"
 
-using namespace dmfe;
+namespace dmfe {
+namespace core {
 
 namespace {
-
 thread_local std::string g_last_error;
+}  // namespace
 
-// Real-axis stability limits of the two RK schemes (|R(-x)| <= 1 on [0, limit]),
-// truncated: Dormand-Prince 5 and SSPRK(10,4).
-constexpr double kDp5Limit = 3.3065;
-constexpr double kSspLimit = 13.917;
+void set_error(const std::string& msg) { g_last_error = msg; }
+const char* last_error() { return g_last_error.c_str(); }
 
 constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
-
-// Butcher tableau of up to 10 stages with the embedded error weights e = b - bhat.
-struct Tableau {
-    int S = 0;
-    double A[10][10] = {};
-    double b[10] = {};
-    double e[10] = {};
-    double c[10] = {};
-    bool fsal = false;  // last stage is evaluated at y_new (c = 1, last row of A = b)
-};
 
 // Dormand-Prince 5(4) (Sec. 3.5).
 Tableau make_dp5() {
@@ -125,11 +114,6 @@ Tableau make_ssprk104() {
     return T;
 }
 
-struct Layout {
-    size_t hist, thist, slot, th, thc, nu, y, ys, ynew, k, mue, eps, diag, eps_n, obs, rhs_y, rhs_k, io, total;
-    // uniform
-    size_t uC, uR, uE, uy0, uy1, uys, uk;
-};
 
 Layout make_layout(const dmfe_params& p) {
     Layout lo{};
@@ -141,12 +125,14 @@ Layout make_layout(const dmfe_params& p) {
     };
     if (p.mode == DMFE_ADAPTIVE) {
         const size_t L = size_t(p.L), Mc = size_t(p.M_cap > 0 ? p.M_cap : p.L);
-        lo.hist = take(Mc * L * sizeof(HPoint));
+        lo.hist = take(Mc * L * (p.precision == DMFE_FP32_COMP ? sizeof(HPoint32) : sizeof(HPoint)));
         lo.thist = take(Mc * sizeof(double));
         lo.slot = take(Mc * sizeof(int));
         lo.th = take(L * sizeof(double));
         lo.thc = take(L * sizeof(double));
         lo.nu = take(L * sizeof(double));
+        lo.X = take(L * L * sizeof(double));
+        lo.Xd = take(L * L * sizeof(double));
         lo.y = take(L * sizeof(YPoint));
         lo.ys = take(L * sizeof(YPoint));
         lo.ynew = take(L * sizeof(YPoint));
@@ -197,7 +183,7 @@ dmfe_status validate(const dmfe_params* p) {
     if (!(p->eps > 0.0) || !(p->dt0 > 0.0) || !(p->dt_min >= 0.0) || p->dt_min >= p->dt0) return DMFE_ERR_INVALID;
     if (p->auto_passes < 0 || p->scheme_policy < 0 || p->scheme_policy > 2) return DMFE_ERR_INVALID;
     if (p->grid_alpha != 0.0) return DMFE_ERR_UNSUPPORTED;
-    if (p->precision != DMFE_FP64) return DMFE_ERR_UNSUPPORTED;
+    if (p->precision != DMFE_FP64 && p->precision != DMFE_FP32_COMP) return DMFE_ERR_INVALID;
     return DMFE_OK;
 }
 
@@ -223,66 +209,64 @@ double f2_at_one(const Model& m) {
     return s;
 }
 
-}  // namespace
 
-struct dmfe_handle {
-    dmfe_params p{};
-    Layout lo{};
-    int device = 0;
-    hipStream_t stream = nullptr;
-    char* base = nullptr;
-    bool owns = false;
-    Model m{};
-    // adaptive
-    int L = 0, s = 10, Mc = 0;
-    double gamma = 0, Dg = 0, xscale = 0, eg = 0, egi = 0;
-    std::vector<double> th, thc, nu;
-    std::vector<double> thist;  // logical order
-    std::vector<int> slot;      // logical order
-    std::vector<int> free_slots;
-    int M = 0, nb_valid = 0;
-    double t = 0, dt = 0, eps_rk = 0;
-    int scheme = DMFE_SCHEME_DP5;
-    bool fsal_valid = false;
-    Tableau dp5, ssp;
-    double* pinned = nullptr;  // host staging for small readbacks
-    // uniform
-    int64_t un = 0;  // rows stored - 1
-    int ucur = 0;    // which of uy0/uy1 holds the current row
-    // counters
-    int64_t accepted = 0, rejected = 0, reverts = 0, n_sparsify = 0, removed = 0, rhs_evals = 0;
-
-    template <class T> T* at(size_t off) const { return reinterpret_cast<T*>(base + off); }
-};
-
-namespace {
 
 dmfe_status fail(hipError_t e, const char* what) {
-    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
     return DMFE_ERR_DEVICE;
 }
-#define HCHK(expr)                                  \
-    do {                                            \
-        hipError_t e_ = (expr);                     \
-        if (e_ != hipSuccess) return fail(e_, #expr); \
-    } while (0)
 
-StageArgs stage_args(const dmfe_handle* h, double t, int nb, const YPoint* y, YPoint* kout, HPoint* store) {
+// Event pair around one launch when timing is on; nullptr otherwise.
+dmfe_handle::EvPair* timing_begin(dmfe_handle* h, int kernel, int64_t slices) {
+    if (!h->timing) return nullptr;
+    dmfe_handle::EvPair p;
+    if (!h->ev_pool.empty()) {
+        p = h->ev_pool.back();
+        h->ev_pool.pop_back();
+    } else if (hipEventCreate(&p.a) != hipSuccess || hipEventCreate(&p.b) != hipSuccess) {
+        return nullptr;
+    }
+    p.kernel = kernel;
+    p.slices = slices;
+    if (hipEventRecord(p.a, h->stream) != hipSuccess) {
+        h->ev_pool.push_back(p);
+        return nullptr;
+    }
+    h->ev_pending.push_back(p);
+    return &h->ev_pending.back();
+}
+void timing_end(dmfe_handle* h, dmfe_handle::EvPair* p) {
+    if (p) (void)hipEventRecord(p->b, h->stream);
+}
+// Accumulate finished event pairs (the stream has been synchronised).
+void timing_drain(dmfe_handle* h) {
+    for (auto& p : h->ev_pending) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            h->kt_launches[p.kernel] += 1;
+            h->kt_ms[p.kernel] += ms;
+            h->kt_slices[p.kernel] += p.slices;
+        }
+        h->ev_pool.push_back(p);
+    }
+    h->ev_pending.clear();
+}
+
+StageArgs stage_args(const dmfe_handle* h, double t, int nb, const YPoint* y, YPoint* kout, void* store) {
     StageArgs a{};
     a.L = h->L;
     a.nb = nb;
     a.t = t;
     a.tb = nb > 0 ? h->thist[nb - 1] : 0.0;
-    a.xscale = h->xscale;
-    a.eg = h->eg;
-    a.egi = h->egi;
-    a.Dg = h->Dg;
+    a.X = h->at<double>(h->lo.X);
+    a.Xd = h->at<double>(h->lo.Xd);
     a.th = h->at<double>(h->lo.th);
     a.thc = h->at<double>(h->lo.thc);
     a.nu = h->at<double>(h->lo.nu);
     a.thist = h->at<double>(h->lo.thist);
     a.slot = h->at<int>(h->lo.slot);
-    a.hist = h->at<HPoint>(h->lo.hist);
+    a.hist = h->at<void>(h->lo.hist);
+    a.fp32 = h->fp32;
     a.y = y;
     a.mue = h->at<double>(h->lo.mue);
     a.kout = kout;
@@ -293,14 +277,21 @@ StageArgs stage_args(const dmfe_handle* h, double t, int nb, const YPoint* y, YP
 }
 
 // one right-hand-side evaluation: mu(t) then the history integrals
-dmfe_status eval_rhs(dmfe_handle* h, double t, int nb, const YPoint* y, YPoint* kout, HPoint* store) {
+dmfe_status eval_rhs(dmfe_handle* h, double t, int nb, const YPoint* y, YPoint* kout, void* store) {
+    auto* e1 = timing_begin(h, DMFE_K_STAGE_PREP, 0);
     HCHK(launch_stage_prep(h->m, h->L, t, h->at<double>(h->lo.nu), y, h->at<double>(h->lo.mue), h->stream));
+    timing_end(h, e1);
+    auto* e2 = timing_begin(h, DMFE_K_HIST_INTEGRAL, nb);
     HCHK(launch_hist_integral(stage_args(h, t, nb, y, kout, store), h->s, h->stream));
+    timing_end(h, e2);
     h->rhs_evals += 1;
     return DMFE_OK;
 }
 
-HPoint* slot_ptr(dmfe_handle* h, int slot) { return h->at<HPoint>(h->lo.hist) + size_t(slot) * h->L; }
+size_t point_bytes(const dmfe_handle* h) { return h->fp32 ? sizeof(HPoint32) : sizeof(HPoint); }
+void* slot_ptr(dmfe_handle* h, int slot) {
+    return h->at<char>(h->lo.hist) + size_t(slot) * h->L * point_bytes(h);
+}
 
 dmfe_status upload_order(dmfe_handle* h) {
     HCHK(hipMemcpyAsync(h->at<double>(h->lo.thist), h->thist.data(), sizeof(double) * h->M, hipMemcpyHostToDevice,
@@ -318,8 +309,10 @@ dmfe_status sparsify_pass(dmfe_handle* h, int64_t* removed_out) {
     if (M < 13) return DMFE_OK;
     const int count = M - 12;  // candidates 1..M-12
     double* eps_n = h->at<double>(h->lo.eps_n);
+    auto* ev = timing_begin(h, DMFE_K_SPARSIFY, 0);
     HCHK(launch_sparsify_residual(h->L, 1, count, h->at<double>(h->lo.thist), h->at<int>(h->lo.slot),
-                                  h->at<HPoint>(h->lo.hist), eps_n, h->stream));
+                                  h->at<void>(h->lo.hist), h->fp32, eps_n, h->stream));
+    timing_end(h, ev);
     std::vector<double> e(M, -1.0);
     HCHK(hipMemcpyAsync(e.data() + 1, eps_n + 1, sizeof(double) * count, hipMemcpyDeviceToHost, h->stream));
     HCHK(hipStreamSynchronize(h->stream));
@@ -374,50 +367,76 @@ void fill_info(const dmfe_handle* h, dmfe_step_info* info) {
 }
 
 // ------------------------------------------------------------------ adaptive stepping
-dmfe_status adaptive_step_once(dmfe_handle* h) {
-    const int L = h->L;
+dmfe_status step_begin(dmfe_handle* h) {
     if (h->M >= h->Mc) {
         int64_t got = 0;
         const int passes = h->p.auto_passes > 0 ? h->p.auto_passes : 1;
         for (int q = 0; q < passes; ++q) {
             int64_t r = 0;
-            dmfe_status st = sparsify_pass(h, &r);
+            const dmfe_status st = sparsify_pass(h, &r);
             if (st != DMFE_OK) return st;
             got += r;
         }
         if (got == 0) return DMFE_ERR_CAPACITY;
     }
-    const Tableau& T = h->scheme == DMFE_SCHEME_DP5 ? h->dp5 : h->ssp;
-    const int M = h->M;
-    const double dt = h->dt, tn = h->thist[M - 1];
+    auto& c = h->cur;
+    c.T = h->scheme == DMFE_SCHEME_DP5 ? &h->dp5 : &h->ssp;
+    c.M = h->M;
+    c.dt = h->dt;
+    c.tn = h->thist[h->M - 1];
+    c.next_slot = h->free_slots.back();
+    c.st = 0;
+    c.active = 1;
+    return DMFE_OK;
+}
+
+dmfe_status step_stage(dmfe_handle* h) {
+    auto& c = h->cur;
+    const Tableau& T = *c.T;
+    const int L = h->L, st = c.st;
     YPoint* y0 = h->at<YPoint>(h->lo.y);
     YPoint* ys = h->at<YPoint>(h->lo.ys);
     YPoint* kb = h->at<YPoint>(h->lo.k);
-    const int next_slot = h->free_slots.back();
-    for (int st = 0; st < T.S; ++st) {
-        YPoint* kst = kb + size_t(st) * L;
-        const double tst = tn + T.c[st] * dt;
-        if (st == 0) {
-            if (h->fsal_valid) {
-                HCHK(hipMemcpyAsync(kst, kb + size_t(6) * L, sizeof(YPoint) * L, hipMemcpyDeviceToDevice, h->stream));
-            } else {
-                dmfe_status s = eval_rhs(h, tst, M - 1, y0, kst, slot_ptr(h, h->slot[M - 1]));
-                if (s != DMFE_OK) return s;
-            }
-            continue;
+    YPoint* kst = kb + size_t(st) * L;
+    const double tst = c.tn + T.c[st] * c.dt;
+    if (st == 0) {
+        if (h->fsal_valid) {
+            HCHK(hipMemcpyAsync(kst, kb + size_t(6) * L, sizeof(YPoint) * L, hipMemcpyDeviceToDevice, h->stream));
+        } else {
+            const dmfe_status s = eval_rhs(h, tst, c.M - 1, y0, kst, slot_ptr(h, h->slot[c.M - 1]));
+            if (s != DMFE_OK) return s;
         }
-        HCHK(launch_rk_combine(L, y0, kb, st, T.A[st], dt, ys, h->stream));
+    } else {
+        auto* ev = timing_begin(h, DMFE_K_RK, 0);
+        HCHK(launch_rk_combine(L, y0, kb, st, T.A[st], c.dt, ys, h->stream));
+        timing_end(h, ev);
         // the last DP5 stage is F(t + dt, y_new): it is also the stored d/dt of the next slice
-        HPoint* store = (T.fsal && st == T.S - 1) ? slot_ptr(h, next_slot) : nullptr;
-        dmfe_status s = eval_rhs(h, tst, M, ys, kst, store);
+        void* store = (T.fsal && st == T.S - 1) ? slot_ptr(h, c.next_slot) : nullptr;
+        const dmfe_status s = eval_rhs(h, tst, c.M, ys, kst, store);
         if (s != DMFE_OK) return s;
     }
-    h->nb_valid = M;
-    YPoint* ynew = h->at<YPoint>(h->lo.ynew);
-    HCHK(launch_rk_finish(L, y0, kb, T.S, T.b, T.e, dt, ynew, h->at<double>(h->lo.eps), h->stream));
+    c.st = st + 1;
+    return DMFE_OK;
+}
+
+dmfe_status step_finish(dmfe_handle* h) {
+    auto& c = h->cur;
+    const Tableau& T = *c.T;
+    auto* evf = timing_begin(h, DMFE_K_RK, 0);
+    HCHK(launch_rk_finish(h->L, h->at<YPoint>(h->lo.y), h->at<YPoint>(h->lo.k), T.S, T.b, T.e, c.dt,
+                          h->at<YPoint>(h->lo.ynew), h->at<double>(h->lo.eps), h->stream));
+    timing_end(h, evf);
     HCHK(hipMemcpyAsync(h->pinned, h->at<double>(h->lo.eps), sizeof(double), hipMemcpyDeviceToHost, h->stream));
-    HCHK(hipStreamSynchronize(h->stream));
-    const double err = h->pinned[0];
+    return DMFE_OK;
+}
+
+dmfe_status step_decide(dmfe_handle* h, double err) {
+    auto& c = h->cur;
+    const Tableau& T = *c.T;
+    const int L = h->L, M = c.M;
+    const double dt = c.dt, tn = c.tn;
+    c.active = 0;
+    h->nb_valid = M;
     h->eps_rk = err;
     dmfe_control ctl{};
     ctl.eps = h->p.eps;
@@ -430,20 +449,24 @@ dmfe_status adaptive_step_once(dmfe_handle* h) {
     int32_t acc = 0, nrev = 0;
     const dmfe_status cs = dmfe_control_update(&ctl, err, &acc, &nrev);
     if (cs == DMFE_ERR_NONFINITE) return cs;
+    YPoint* y0 = h->at<YPoint>(h->lo.y);
     if (acc) {
+        const int slot = c.next_slot;
         h->free_slots.pop_back();
-        HCHK(launch_append(L, ynew, slot_ptr(h, next_slot), h->stream));
+        HCHK(launch_append(L, h->at<YPoint>(h->lo.ynew), slot_ptr(h, slot), h->fp32, h->stream));
         h->thist.push_back(tn + dt);
-        h->slot.push_back(next_slot);
+        h->slot.push_back(slot);
         h->M = M + 1;
         h->nb_valid = T.fsal ? h->M : M;
         h->t = tn + dt;
-        // ynew becomes the state
-        HCHK(hipMemcpyAsync(y0, ynew, sizeof(YPoint) * L, hipMemcpyDeviceToDevice, h->stream));
-        HCHK(hipMemcpyAsync(h->at<double>(h->lo.thist) + M, &h->thist[M], sizeof(double), hipMemcpyHostToDevice,
+        // ynew becomes the state; the new slice's time and slot go to the device index arrays
+        HCHK(hipMemcpyAsync(y0, h->at<YPoint>(h->lo.ynew), sizeof(YPoint) * L, hipMemcpyDeviceToDevice, h->stream));
+        double* stage = h->pinned + 8 + 2 * (h->accepted & 1);  // alternating staging cells
+        stage[0] = h->t;
+        std::memcpy(&stage[1], &slot, sizeof(int));
+        HCHK(hipMemcpyAsync(h->at<double>(h->lo.thist) + M, &stage[0], sizeof(double), hipMemcpyHostToDevice,
                             h->stream));
-        HCHK(hipMemcpyAsync(h->at<int>(h->lo.slot) + M, &h->slot[M], sizeof(int), hipMemcpyHostToDevice, h->stream));
-        HCHK(hipStreamSynchronize(h->stream));
+        HCHK(hipMemcpyAsync(h->at<int>(h->lo.slot) + M, &stage[1], sizeof(int), hipMemcpyHostToDevice, h->stream));
         h->fsal_valid = T.fsal;
         h->accepted += 1;
     } else {
@@ -455,7 +478,7 @@ dmfe_status adaptive_step_once(dmfe_handle* h) {
         h->M = M - nrev;
         h->nb_valid = std::min(h->nb_valid, h->M);
         h->t = h->thist[h->M - 1];
-        HCHK(launch_load_state(L, slot_ptr(h, h->slot[h->M - 1]), y0, h->stream));
+        HCHK(launch_load_state(L, slot_ptr(h, h->slot[h->M - 1]), h->fp32, y0, h->stream));
         h->fsal_valid = false;
         h->rejected += 1;
         h->reverts += nrev;
@@ -465,9 +488,23 @@ dmfe_status adaptive_step_once(dmfe_handle* h) {
     return cs;
 }
 
+dmfe_status adaptive_step_once(dmfe_handle* h) {
+    dmfe_status st = step_begin(h);
+    if (st != DMFE_OK) return st;
+    while (h->cur.st < h->cur.T->S) {
+        st = step_stage(h);
+        if (st != DMFE_OK) return st;
+    }
+    st = step_finish(h);
+    if (st != DMFE_OK) return st;
+    HCHK(hipStreamSynchronize(h->stream));
+    timing_drain(h);
+    return step_decide(h, h->pinned[0]);
+}
+
 dmfe_status adaptive_step(dmfe_handle* h, double t_target, int64_t max_steps) {
     for (int64_t k = 0; k < max_steps; ++k) {
-        if (h->t >= t_target) break;
+        if (h->t >= t_target || h->t >= h->p.t_max) break;
         const dmfe_status st = adaptive_step_once(h);
         if (st != DMFE_OK) return st;
     }
@@ -520,9 +557,12 @@ dmfe_status uniform_step(dmfe_handle* h, double t_target, int64_t max_steps) {
     return h->un >= N ? DMFE_DONE : DMFE_OK;
 }
 
-}  // namespace
+}  // namespace core
+}  // namespace dmfe
 
-// ====================================================================== C-ABI
+using namespace dmfe;
+using namespace dmfe::core;
+
 extern "C" {
 
 const char* dmfe_status_string(dmfe_status s) {
@@ -541,7 +581,7 @@ const char* dmfe_status_string(dmfe_status s) {
     }
 }
 
-const char* dmfe_last_error(void) { return g_last_error.c_str(); }
+const char* dmfe_last_error(void) { return last_error(); }
 
 dmfe_status dmfe_footprint(const dmfe_params* params, size_t* bytes) {
     const dmfe_status v = validate(params);
@@ -640,7 +680,7 @@ dmfe_status dmfe_create(const dmfe_params* params, const dmfe_resources* res, dm
         e = hipMalloc(reinterpret_cast<void**>(&h->base), h->lo.total);
         if (e != hipSuccess) {
             h->base = nullptr;
-            g_last_error = std::string("hipMalloc: ") + hipGetErrorString(e);
+            set_error(std::string("hipMalloc: ") + hipGetErrorString(e));
             return bail(DMFE_ERR_NOMEM);
         }
         h->owns = true;
@@ -676,6 +716,7 @@ dmfe_status dmfe_create(const dmfe_params* params, const dmfe_resources* res, dm
     h->L = h->p.L;
     h->s = h->p.s;
     h->Mc = h->p.M_cap;
+    h->fp32 = h->p.precision == DMFE_FP32_COMP ? 1 : 0;
     const int L = h->L;
     h->th.resize(L);
     h->thc.resize(L);
@@ -698,8 +739,23 @@ dmfe_status dmfe_create(const dmfe_params* params, const dmfe_resources* res, dm
         (e = hipMemcpyAsync(h->at<double>(h->lo.nu), h->nu.data(), sizeof(double) * L, hipMemcpyHostToDevice,
                             h->stream)))
         return bail(fail(e, "hipMemcpyAsync"));
+    {
+        GridArgs g{};
+        g.L = L;
+        g.xscale = h->xscale;
+        g.eg = h->eg;
+        g.egi = h->egi;
+        g.Dg = h->Dg;
+        g.th = h->at<double>(h->lo.th);
+        g.thc = h->at<double>(h->lo.thc);
+        g.X = h->at<double>(h->lo.X);
+        g.Xd = h->at<double>(h->lo.Xd);
+        e = launch_coords(g, h->stream);
+        if (e != hipSuccess) return bail(fail(e, "coordinate precompute"));
+    }
     // initial slice t = 0: C = R = 1 (derivative filled at the first stage)
     std::vector<HPoint> s0(L, HPoint{1.0, 1.0, 0.0, 0.0});
+    std::vector<HPoint32> s032(L, HPoint32{1.0f, 1.0f, 0.0f, 0.0f});
     std::vector<YPoint> y0(L, YPoint{1.0, 1.0});
     h->free_slots.clear();
     for (int q = h->Mc - 1; q >= 1; --q) h->free_slots.push_back(q);
@@ -708,7 +764,8 @@ dmfe_status dmfe_create(const dmfe_params* params, const dmfe_resources* res, dm
     h->M = 1;
     h->nb_valid = 0;
     h->t = 0.0;
-    if ((e = hipMemcpyAsync(slot_ptr(h, 0), s0.data(), sizeof(HPoint) * L, hipMemcpyHostToDevice, h->stream)) ||
+    if ((e = hipMemcpyAsync(slot_ptr(h, 0), h->fp32 ? static_cast<const void*>(s032.data()) : s0.data(),
+                            point_bytes(h) * L, hipMemcpyHostToDevice, h->stream)) ||
         (e = hipMemcpyAsync(h->at<YPoint>(h->lo.y), y0.data(), sizeof(YPoint) * L, hipMemcpyHostToDevice,
                             h->stream)))
         return bail(fail(e, "hipMemcpyAsync"));
@@ -725,6 +782,11 @@ void dmfe_destroy(dmfe_handle* h) {
     else (void)hipDeviceSynchronize();
     if (h->owns && h->base) (void)hipFree(h->base);
     if (h->pinned) (void)hipHostFree(h->pinned);
+    for (auto* v : {&h->ev_pool, &h->ev_pending})
+        for (auto& p : *v) {
+            if (p.a) (void)hipEventDestroy(p.a);
+            if (p.b) (void)hipEventDestroy(p.b);
+        }
     delete h;
 }
 
@@ -786,16 +848,23 @@ dmfe_status dmfe_set_history(dmfe_handle* h, int64_t M, int64_t nb, const double
     dmfe_status st = upload_order(h);
     if (st != DMFE_OK) return st;
     if (src_on_device) {
-        HCHK(launch_unpack_history(L, int(M), C, R, dC, dR, h->at<int>(h->lo.slot), h->at<HPoint>(h->lo.hist),
+        HCHK(launch_unpack_history(L, int(M), C, R, dC, dR, h->at<int>(h->lo.slot), h->at<void>(h->lo.hist), h->fp32,
                                    h->stream));
+    } else if (h->fp32) {
+        std::vector<HPoint32> buf(size_t(M) * L);
+        for (size_t q = 0; q < buf.size(); ++q)
+            buf[q] = HPoint32{float(C[q]), float(R[q]), float(dC[q]), float(dR[q])};
+        HCHK(hipMemcpyAsync(h->at<void>(h->lo.hist), buf.data(), sizeof(HPoint32) * buf.size(),
+                            hipMemcpyHostToDevice, h->stream));
+        HCHK(hipStreamSynchronize(h->stream));
     } else {
         std::vector<HPoint> buf(size_t(M) * L);
         for (size_t q = 0; q < buf.size(); ++q) buf[q] = HPoint{C[q], R[q], dC[q], dR[q]};
-        HCHK(hipMemcpyAsync(h->at<HPoint>(h->lo.hist), buf.data(), sizeof(HPoint) * buf.size(),
+        HCHK(hipMemcpyAsync(h->at<void>(h->lo.hist), buf.data(), sizeof(HPoint) * buf.size(),
                             hipMemcpyHostToDevice, h->stream));
         HCHK(hipStreamSynchronize(h->stream));
     }
-    HCHK(launch_load_state(L, slot_ptr(h, h->slot[M - 1]), h->at<YPoint>(h->lo.y), h->stream));
+    HCHK(launch_load_state(L, slot_ptr(h, h->slot[M - 1]), h->fp32, h->at<YPoint>(h->lo.y), h->stream));
     HCHK(hipStreamSynchronize(h->stream));
     h->nb_valid = int(nb);
     h->t = th[M - 1];
@@ -913,8 +982,8 @@ dmfe_status dmfe_read(dmfe_handle* h, int32_t field, int64_t first, int64_t coun
         double* io = h->at<double>(h->lo.io);
         for (int64_t n0 = 0; n0 < count; n0 += 64) {
             const int cnt = int(std::min<int64_t>(64, count - n0));
-            HCHK(launch_pack_history(L, cnt, fld, h->at<int>(h->lo.slot) + first + n0, h->at<HPoint>(h->lo.hist), io,
-                                     h->stream));
+            HCHK(launch_pack_history(L, cnt, fld, h->at<int>(h->lo.slot) + first + n0, h->at<void>(h->lo.hist),
+                                     h->fp32, io, h->stream));
             HCHK(hipMemcpyAsync(static_cast<char*>(dst) + size_t(n0) * L * sizeof(double), io,
                                 size_t(cnt) * L * sizeof(double), kind, h->stream));
             HCHK(hipStreamSynchronize(h->stream));
@@ -931,13 +1000,44 @@ dmfe_status dmfe_read(dmfe_handle* h, int32_t field, int64_t first, int64_t coun
         double* Eo = h->at<double>(h->lo.obs);
         double* Mo = Eo + h->Mc;
         HCHK(launch_slice_observables(h->m, L, h->at<double>(h->lo.nu), int(count), h->at<double>(h->lo.thist) + first,
-                                      h->at<int>(h->lo.slot) + first, h->at<HPoint>(h->lo.hist), Eo, Mo, h->stream));
+                                      h->at<int>(h->lo.slot) + first, h->at<void>(h->lo.hist), h->fp32, Eo, Mo,
+                                      h->stream));
         HCHK(hipMemcpyAsync(dst, field == DMFE_F_ENERGY ? Eo : Mo, need, kind, h->stream));
         break;
     }
     default: return DMFE_ERR_INVALID;
     }
     HCHK(hipStreamSynchronize(h->stream));
+    return DMFE_OK;
+}
+
+dmfe_status dmfe_timing(dmfe_handle* h, int32_t enable) {
+    if (!h) return DMFE_ERR_INVALID;
+    hipError_t e = hipSetDevice(h->device);
+    if (e != hipSuccess) return fail(e, "hipSetDevice");
+    HCHK(hipStreamSynchronize(h->stream));
+    timing_drain(h);
+    if (enable) {
+        for (int k = 0; k < DMFE_K_COUNT; ++k) {
+            h->kt_launches[k] = 0;
+            h->kt_ms[k] = 0.0;
+            h->kt_slices[k] = 0;
+        }
+    }
+    h->timing = enable != 0;
+    return DMFE_OK;
+}
+
+dmfe_status dmfe_timing_read(dmfe_handle* h, int32_t kernel, int64_t* launches, double* total_ms,
+                             int64_t* slices_read) {
+    if (!h || kernel < 0 || kernel >= DMFE_K_COUNT) return DMFE_ERR_INVALID;
+    hipError_t e = hipSetDevice(h->device);
+    if (e != hipSuccess) return fail(e, "hipSetDevice");
+    HCHK(hipStreamSynchronize(h->stream));
+    timing_drain(h);
+    if (launches) *launches = h->kt_launches[kernel];
+    if (total_ms) *total_ms = h->kt_ms[kernel];
+    if (slices_read) *slices_read = h->kt_slices[kernel];
     return DMFE_OK;
 }
 

@@ -32,6 +32,10 @@ struct Model {
 struct alignas(32) HPoint {
     double c, r, dc, dr;
 };
+// The same point stored in single precision (DMFE_FP32_COMP histories).
+struct alignas(16) HPoint32 {
+    float c, r, dc, dr;
+};
 // One point of a stage slice (the RK state vector is interleaved C, R).
 struct alignas(16) YPoint {
     double c, r;
@@ -43,24 +47,37 @@ struct StageArgs {
     int nb;              // slices 0..nb-1 carry valid d/dt
     double t;            // stage time
     double tb;           // t of slice nb-1 (unused when nb == 0)
-    double xscale;       // (L-1) / (2 gamma)
-    double eg, egi;      // e^gamma, e^{-gamma}
-    double Dg;           // atan(sinh gamma)
+    const double* X;     // X[j][i] = x(theta_i theta_j), continuous grid index [L][L]
+    const double* Xd;    // Xd[j][i] = x(psi_ij), psi = theta_j / phi_ij [L][L]
     const double* th;    // theta_i [L]
     const double* thc;   // 1 - theta_i [L]
     const double* nu;    // quadrature weights [L]
     const double* thist; // t_n in logical order [>= nb]
     const int* slot;     // slot of logical slice n [>= nb]
-    const HPoint* hist;  // history slots [M_cap][L]
+    const void* hist;    // history slots [M_cap][L] of HPoint (fp64) or HPoint32 (fp32 histories)
     const YPoint* y;     // stage slice [L]
     const double* mue;   // mu(t), E(t) of the stage slice [2]
     YPoint* kout;        // d/dt C, d/dt R along fixed theta [L]
-    HPoint* store;       // if not null: slot whose dc, dr receive kout (row L-1 stored as 0)
+    void* store;         // if not null: slot whose dc, dr receive kout (row L-1 stored as 0)
+    int fp32;            // history precision: 0 = HPoint, 1 = HPoint32
     double* diag;        // computed values of row L-1 [2]
     Model m;
 };
 
+// Run-constant data of the theta grid used by the coordinate precompute.
+struct GridArgs {
+    int L;
+    double xscale;  // (L-1) / (2 gamma)
+    double eg, egi; // e^gamma, e^{-gamma}
+    double Dg;      // atan(sinh gamma)
+    const double* th;
+    const double* thc;
+    double* X;
+    double* Xd;
+};
+
 // launchers (kernels_theta.hip); all return hipError_t of the launch
+hipError_t launch_coords(const GridArgs& g, hipStream_t st);
 hipError_t launch_stage_prep(const Model& m, int L, double t, const double* nu, const YPoint* y, double* mue,
                              hipStream_t st);
 hipError_t launch_hist_integral(const StageArgs& a, int s, hipStream_t st);
@@ -68,18 +85,56 @@ hipError_t launch_rk_combine(int L, const YPoint* y0, const YPoint* k, int nk, c
                              YPoint* ys, hipStream_t st);
 hipError_t launch_rk_finish(int L, const YPoint* y0, const YPoint* k, int nk, const double* b, const double* e,
                             double dt, YPoint* ynew, double* eps_out, hipStream_t st);
-hipError_t launch_append(int L, const YPoint* y, HPoint* slot_dst, hipStream_t st);
-hipError_t launch_load_state(int L, const HPoint* slot_src, YPoint* y, hipStream_t st);
+// History pointers below are HPoint* when fp32 == 0 and HPoint32* when fp32 == 1.
+hipError_t launch_append(int L, const YPoint* y, void* slot_dst, int fp32, hipStream_t st);
+hipError_t launch_load_state(int L, const void* slot_src, int fp32, YPoint* y, hipStream_t st);
 hipError_t launch_sparsify_residual(int L, int first, int count, const double* thist, const int* slot,
-                                    const HPoint* hist, double* eps_n, hipStream_t st);
+                                    const void* hist, int fp32, double* eps_n, hipStream_t st);
 hipError_t launch_slice_observables(const Model& m, int L, const double* nu, int count, const double* thist,
-                                    const int* slot, const HPoint* hist, double* E, double* mu, hipStream_t st);
-hipError_t launch_pack_history(int L, int count, int field, const int* slot, const HPoint* hist, double* dst,
-                               hipStream_t st);
+                                    const int* slot, const void* hist, int fp32, double* E, double* mu,
+                                    hipStream_t st);
+hipError_t launch_pack_history(int L, int count, int field, const int* slot, const void* hist, int fp32,
+                               double* dst, hipStream_t st);
 hipError_t launch_unpack_history(int L, int count, const double* C, const double* R, const double* dC,
-                                 const double* dR, const int* slot, HPoint* hist, hipStream_t st);
+                                 const double* dR, const int* slot, void* hist, int fp32, hipStream_t st);
 hipError_t launch_interleave(int L, const double* a, const double* b, YPoint* y, hipStream_t st);
 hipError_t launch_deinterleave(int L, const YPoint* y, double* a, double* b, hipStream_t st);
+
+// ---------------------------------------------------------------- many instances per launch (serving)
+// Block b of a batched launch belongs to instance q with first_block[q] <= b < first_block[q+1].
+struct CombineDesc {
+    const YPoint* y0;
+    const YPoint* k;
+    YPoint* ys;
+    int L, nk;
+    double dt;
+    double a[10];
+};
+struct PrepDesc {
+    const YPoint* y;
+    const double* nu;
+    double* mue;
+    int L;
+    double t;
+    Model m;
+};
+struct FinishDesc {
+    const YPoint* y0;
+    const YPoint* k;
+    YPoint* ynew;
+    double* eps;
+    int L, nk;
+    double dt;
+    double b[10], e[10];
+};
+hipError_t launch_rk_combine_multi(const CombineDesc* d, const int* first_block, int n, int total_blocks,
+                                   hipStream_t st);
+hipError_t launch_stage_prep_multi(const PrepDesc* d, int n, int pmax, hipStream_t st);
+hipError_t launch_hist_integral_multi(const StageArgs* d, const int* first_block, int n, int total_blocks, int s,
+                                      int pmax, int fp32, int nb_max, hipStream_t st);
+hipError_t launch_rk_finish_multi(const FinishDesc* d, int n, hipStream_t st);
+constexpr int kCombineBlock = 256;
+constexpr int kHistRowsPerBlock = 8;
 
 // ---------------------------------------------------------------- uniform mode (kernels_uniform.hip)
 struct UniArgs {

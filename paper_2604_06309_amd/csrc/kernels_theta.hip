@@ -55,7 +55,7 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 // Continuous 0-based index of theta on the grid (inverse of eq. theta at
 // alpha = 0): x = (L-1)/(2g) [log1p(e^g T) - log1p(-e^{-g} T)], T = tan(theta D)
 // for theta <= 1/2; x = L-1 - x(1-theta) above, with the complement passed in.
-__device__ __forceinline__ double xmap(const StageArgs& a, double th, double thc) {
+__device__ __forceinline__ double xmap(const GridArgs& a, double th, double thc) {
     const bool lower = th <= 0.5;
     const double arg = lower ? th : thc;
     const double T = tan(arg * a.Dg);
@@ -63,33 +63,71 @@ __device__ __forceinline__ double xmap(const StageArgs& a, double th, double thc
     return lower ? x : double(a.L - 1) - x;
 }
 
-// ---------------------------------------------------------------- index Lagrange stencil
-__host__ __device__ constexpr double fact(int n) { return n <= 1 ? 1.0 : double(n) * fact(n - 1); }
-__host__ __device__ constexpr double inv_den(int S, int k) {
-    return (((S - 1 - k) & 1) ? -1.0 : 1.0) / (fact(k) * fact(S - 1 - k));
+// The interpolation coordinates depend only on the grid, so they are formed
+// once per solver: X[j][i] = x(theta_i theta_j) (with its complement
+// 1 - theta_i theta_j = (1-theta_i) + theta_i (1-theta_j)) and
+// Xd[j][i] = x(psi_ij), psi = theta_j/phi, 1 - psi = (1-theta_j) theta_i/phi.
+// Because theta_{L-1-i} = 1 - theta_i on this grid, x(phi_ij) =
+// L-1 - X[L-1-j][L-1-i] and the phi family needs no table of its own.
+__global__ void k_coords(const GridArgs g) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= g.L) return;
+    const double thi = g.th[i], thci = g.thc[i], thj = g.th[j], thcj = g.thc[j];
+    g.X[size_t(j) * g.L + i] = xmap(g, thi * thj, fma(thi, thcj, thci));
+    const double phi = fma(thcj, thi, thj);
+    double psi = 0.0, psic = 1.0;  // psi = 0/0 := 0 at i = j = 0
+    if (phi > 0.0) {
+        psi = thj / phi;
+        psic = thcj * thi / phi;
+    }
+    g.Xd[size_t(j) * g.L + i] = xmap(g, psi, psic);
 }
+
+// ---------------------------------------------------------------- index Lagrange stencil
+// 1 / prod_{l != k} (k - l) = (-1)^(S-1-k) / (k! (S-1-k)!), as a compile-time table
+template <int S>
+struct InvDen {
+    double v[S];
+    constexpr InvDen() : v() {
+        for (int k = 0; k < S; ++k) {
+            double f = 1.0;
+            for (int q = 2; q <= k; ++q) f *= q;
+            for (int q = 2; q <= S - 1 - k; ++q) f *= q;
+            v[k] = (((S - 1 - k) & 1) ? -1.0 : 1.0) / f;
+        }
+    }
+};
 // Weights of the S-point Lagrange interpolant in the index coordinate on nodes
 // base..base+S-1, base = floor(x) - (S-1)/2 clamped to [0, L-S].
-template <int S>
-__device__ __forceinline__ int lagrange(double x, int L, double (&w)[S]) {
+// The offset u = x - base is formed in double; the weights are computed in R.
+template <int S, class R = double>
+__device__ __forceinline__ int lagrange(double x, int L, R (&w)[S]) {
     int base = int(floor(x)) - (S - 1) / 2;
     base = base < 0 ? 0 : (base > L - S ? L - S : base);
-    const double u = x - double(base);
-    double pre[S];
-    double acc = 1.0;
+    const R u = R(x - double(base));
+    constexpr InvDen<S> den{};
+    R pre[S];
+    R acc = R(1);
 #pragma unroll
     for (int k = 0; k < S; ++k) {
         pre[k] = acc;
-        acc *= (u - double(k));
+        acc *= (u - R(k));
     }
-    acc = 1.0;
+    acc = R(1);
 #pragma unroll
     for (int k = S - 1; k >= 0; --k) {
-        w[k] = pre[k] * acc * inv_den(S, k);
-        acc *= (u - double(k));
+        w[k] = pre[k] * acc * R(den.v[k]);
+        acc *= (u - R(k));
     }
     return base;
 }
+
+// Arithmetic type of values read from a history point type.
+template <class HP> struct HReal;
+template <> struct HReal<HPoint> { using type = double; };
+template <> struct HReal<HPoint32> { using type = float; };
+template <class HP> using hreal_t = typename HReal<HP>::type;
 
 template <int S>
 __device__ __forceinline__ void interp2(const YPoint* row, int base, const double (&w)[S], double& c, double& r) {
@@ -102,25 +140,25 @@ __device__ __forceinline__ void interp2(const YPoint* row, int base, const doubl
         r = fma(w[k], v.r, r);
     }
 }
-template <int S>
-__device__ __forceinline__ void interp4(const HPoint* row, int base, const double (&w)[S], HPoint& o) {
-    o.c = o.r = o.dc = o.dr = 0.0;
+template <int S, class HP, class R = hreal_t<HP>>
+__device__ __forceinline__ void interp4(const HP* row, int base, const R (&w)[S], R& c, R& r, R& dc, R& dr) {
+    c = r = dc = dr = R(0);
 #pragma unroll
     for (int k = 0; k < S; ++k) {
-        const HPoint v = row[base + k];
-        o.c = fma(w[k], v.c, o.c);
-        o.r = fma(w[k], v.r, o.r);
-        o.dc = fma(w[k], v.dc, o.dc);
-        o.dr = fma(w[k], v.dr, o.dr);
+        const HP v = row[base + k];
+        c = fma(w[k], v.c, c);
+        r = fma(w[k], v.r, r);
+        dc = fma(w[k], v.dc, dc);
+        dr = fma(w[k], v.dr, dr);
     }
 }
-template <int S>
-__device__ __forceinline__ void interp2h(const HPoint* row, int base, const double (&w)[S], double& c, double& r) {
-    c = 0.0;
-    r = 0.0;
+template <int S, class HP, class R = hreal_t<HP>>
+__device__ __forceinline__ void interp2h(const HP* row, int base, const R (&w)[S], R& c, R& r) {
+    c = R(0);
+    r = R(0);
 #pragma unroll
     for (int k = 0; k < S; ++k) {
-        const HPoint v = row[base + k];
+        const HP v = row[base + k];
         c = fma(w[k], v.c, c);
         r = fma(w[k], v.r, r);
     }
@@ -140,8 +178,8 @@ __device__ __forceinline__ int bracket(const double* t, int lo, int hi, double x
 // mu(t) = T + t sum_i nu_i [f''(C)RC + f'(C)R]_i + beta0 f'(C_0) C_0 and
 // E(t) = -t sum_i nu_i f'(C_i) R_i - beta0 f(C_0) on the stage slice (Sec. 2.1).
 template <int PM>
-__global__ __launch_bounds__(1024) void k_stage_prep(const Model m, int L, double t, const double* __restrict__ nu,
-                                                     const YPoint* __restrict__ y, double* __restrict__ mue) {
+__device__ __forceinline__ void stage_prep_body(const Model& m, int L, double t, const double* __restrict__ nu,
+                                                const YPoint* __restrict__ y, double* __restrict__ mue) {
     __shared__ double sh[16];
     double sk = 0.0, se = 0.0;
     for (int i = threadIdx.x; i < L; i += blockDim.x) {
@@ -158,8 +196,48 @@ __global__ __launch_bounds__(1024) void k_stage_prep(const Model m, int L, doubl
         mue[1] = -t * se - m.beta0 * fF<PM>(m, v0.c);
     }
 }
+template <int PM>
+__global__ __launch_bounds__(1024) void k_stage_prep(const Model m, int L, double t, const double* __restrict__ nu,
+                                                     const YPoint* __restrict__ y, double* __restrict__ mue) {
+    stage_prep_body<PM>(m, L, t, nu, y, mue);
+}
+template <int PM>
+__global__ __launch_bounds__(1024) void k_stage_prep_multi(const PrepDesc* __restrict__ d) {
+    const PrepDesc& q = d[blockIdx.x];
+    stage_prep_body<PM>(q.m, q.L, q.t, q.nu, q.y, q.mue);
+}
 
 // ---------------------------------------------------------------- the history integrals
+// Bracket search acceleration: per block, bk[q] is the bracket (largest m with
+// t_m <= e_q) of the left edge e_q of bucket q of K buckets spaced evenly in
+// log2 t over [t_1, t_b].  A target s falls in bucket ~(log2 s - log2 t_1) K /
+// span, computed in single precision; the bracket is then found by a binary
+// search in double precision between the brackets of neighbouring bucket
+// edges, so the result is exact whatever the rounding of the bucket index.
+constexpr int kBuckets = 512;
+constexpr int kRowsPerBlock = kHistRowsPerBlock;
+
+struct Buckets {
+    float lt1, inv;  // log2 t_1, K / span
+    int on;          // table built (b >= 2)
+};
+
+__device__ __forceinline__ int bracket_fast(const double* t, const int* bk, const Buckets& B, int b, double s) {
+    if (b <= 1 || s < t[1]) return 0;
+    int lo = 0, hi = b;
+    if (B.on) {
+        int q = int((__log2f(float(s)) - B.lt1) * B.inv);
+        q = q < 0 ? 0 : (q > kBuckets ? kBuckets : q);
+        lo = bk[q > 0 ? q - 1 : 0];
+        hi = bk[q + 2 < kBuckets ? q + 2 : kBuckets] + 1;
+        lo = lo > 0 ? lo - 1 : 0;
+        hi = hi + 1 < b ? hi + 1 : b;
+        while (lo > 0 && t[lo] > s) --lo;    // keep t[lo] <= s <= t[hi]
+        while (hi < b && t[hi] < s) ++hi;
+    }
+    return bracket(t, lo, hi, s);
+}
+
 // One wavefront per row j (t' = theta_j t); lanes walk the quadrature nodes i.
 // Per pair (i, j) the kernel forms
 //   a = (C,R)(t, theta_i theta_j t)        index Lagrange on the stage slice
@@ -171,137 +249,181 @@ __global__ __launch_bounds__(1024) void k_stage_prep(const Model m, int L, doubl
 // the last slice with a stored derivative and the stage slice), and the nine
 // nu-weighted row sums of the forward, transposed and dual equations; lane 0
 // assembles d/dt C(t, theta_j t) = d1C + theta_j d2C and likewise for R.
-template <int S, int PM>
-__global__ __launch_bounds__(256) void k_hist_integral(const StageArgs a) {
-    extern __shared__ double s_t[];
+// Body of the history-integral kernel for one block: rows
+// row_block * kRowsPerBlock ... of the instance described by `a`.
+// LDS of one block: t_n of the stored slices [nb], the bucket table [K+1]
+// ints (padded to 8 bytes) and, when YL, the stage slice [L].
+__host__ __device__ inline size_t lds_offset_y(int nb) {
+    return (size_t(nb > 0 ? nb : 1) * 8 + (kBuckets + 2) * 4 + 15) / 16 * 16;
+}
+__host__ __device__ inline size_t lds_bytes(int nb, int L, bool yl) {
+    return lds_offset_y(nb) + (yl ? size_t(L) * 16 : 0);
+}
+
+template <int S, int PM, class HP, bool YL>
+__device__ __forceinline__ void hist_integral_block(const StageArgs& a, int row_block) {
+    using HR = hreal_t<HP>;  // arithmetic on values read from the history
+    extern __shared__ double smem[];
     const int nb = a.nb;
+    const int b = nb - 1;
+    double* s_t = smem;
+    int* s_bk = reinterpret_cast<int*>(smem + (nb > 0 ? nb : 1));
     for (int q = threadIdx.x; q < nb; q += blockDim.x) s_t[q] = a.thist[q];
+    const YPoint* ysrc = a.y;
+    if (YL) {
+        YPoint* s_y = reinterpret_cast<YPoint*>(reinterpret_cast<char*>(smem) + lds_offset_y(nb));
+        for (int q = threadIdx.x; q < a.L; q += blockDim.x) s_y[q] = a.y[q];
+        ysrc = s_y;
+    }
     __syncthreads();
+    Buckets B{0.0f, 0.0f, 0};
+    if (b >= 2) {
+        const float lt1 = __log2f(float(s_t[1])), ltb = __log2f(float(s_t[b]));
+        const float span = ltb - lt1;
+        B.on = span > 0.0f ? 1 : 0;
+        B.lt1 = lt1;
+        B.inv = B.on ? float(kBuckets) / span : 0.0f;
+        if (B.on) {
+            for (int q = threadIdx.x; q <= kBuckets; q += blockDim.x) {
+                const double e = exp2(double(lt1) + double(q) * double(span) / double(kBuckets));
+                int lo = 0;
+                if (e >= s_t[b]) lo = b - 1;
+                else if (e > 0.0) lo = bracket(s_t, 0, b, e);
+                s_bk[q] = lo;
+            }
+        }
+        __syncthreads();
+    }
 
     const int lane = threadIdx.x & (kWave - 1);
-    const int j = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    const int j = row_block * kRowsPerBlock + threadIdx.x / kWave;
     if (j >= a.L) return;
     const int L = a.L;
+    const HP* hist = static_cast<const HP*>(a.hist);
     const double t = a.t, thj = a.th[j], thcj = a.thc[j], tp = thj * t;
-    const int b = nb - 1;
     const double tb = a.tb;
 
     // row bracket for the c family (wave-uniform)
     int cmode;  // 0: stage slice only (t = 0), 1: slice 0, 2: Hermite, 3: in-step quadratic
-    const HPoint* c0p = nullptr;
-    const HPoint* c1p = nullptr;
-    double cw0 = 0.0, cw1 = 0.0, cw2 = 0.0, cw3 = 0.0;
+    const HP* c0p = nullptr;
+    const HP* c1p = nullptr;
+    HR cw0 = 0, cw1 = 0, cw2 = 0, cw3 = 0;
     if (nb == 0) {
         cmode = 0;
     } else if (tp <= tb) {
         if (b == 0) {
             cmode = 1;
-            c0p = a.hist + size_t(a.slot[0]) * L;
+            c0p = hist + size_t(a.slot[0]) * L;
         } else {
             cmode = 2;
             const int m = bracket(s_t, 0, b, tp);
             const double h = s_t[m + 1] - s_t[m];
             const double u = (tp - s_t[m]) / h;
-            cw0 = 2 * u * u * u - 3 * u * u + 1;
-            cw1 = (u * u * u - 2 * u * u + u) * h;
-            cw2 = -2 * u * u * u + 3 * u * u;
-            cw3 = (u * u * u - u * u) * h;
-            c0p = a.hist + size_t(a.slot[m]) * L;
-            c1p = a.hist + size_t(a.slot[m + 1]) * L;
+            cw0 = HR(2 * u * u * u - 3 * u * u + 1);
+            cw1 = HR((u * u * u - 2 * u * u + u) * h);
+            cw2 = HR(-2 * u * u * u + 3 * u * u);
+            cw3 = HR((u * u * u - u * u) * h);
+            c0p = hist + size_t(a.slot[m]) * L;
+            c1p = hist + size_t(a.slot[m + 1]) * L;
         }
     } else {
         cmode = 3;
         const double h = t - tb;
         const double u = (tp - tb) / h;
-        cw0 = 1.0 - u * u;
-        cw1 = h * (u - u * u);
-        cw2 = u * u;
-        c0p = a.hist + size_t(a.slot[b]) * L;
+        cw0 = HR(1.0 - u * u);
+        cw1 = HR(h * (u - u * u));
+        cw2 = HR(u * u);
+        c0p = hist + size_t(a.slot[b]) * L;
     }
-    const HPoint* bslot = nb >= 1 ? a.hist + size_t(a.slot[b]) * L : nullptr;
-    const HPoint* slot0 = nb >= 1 ? a.hist + size_t(a.slot[0]) * L : nullptr;
+    const HP* bslot = nb >= 1 ? hist + size_t(a.slot[b]) * L : nullptr;
+    const HP* slot0 = nb >= 1 ? hist + size_t(a.slot[0]) * L : nullptr;
     const double hq = t - tb;
+    const double* Xa = a.X + size_t(j) * L;          // row j, read forwards
+    const double* Xb = a.X + size_t(L - 1 - j) * L;  // row L-1-j, read backwards
+    const double* Xdj = a.Xd + size_t(j) * L;
 
     double S1 = 0, S2 = 0, S3 = 0, S4 = 0, S5 = 0, S6 = 0, S7 = 0, S8 = 0, S9 = 0;
     double c0C = 0.0;
-    int lo = 0;
+#pragma unroll 1
     for (int i = lane; i < L; i += kWave) {
-        const double thi = a.th[i], thci = a.thc[i], w = a.nu[i];
+        const double thi = a.th[i], w = a.nu[i];
         double wl[S];
         // a: (t, theta_i theta_j)
         double aC, aR;
         {
-            const double x = xmap(a, thi * thj, fma(thi, thcj, thci));
-            const int base = lagrange<S>(x, L, wl);
-            interp2<S>(a.y, base, wl, aC, aR);
+            const int base = lagrange<S>(Xa[i], L, wl);
+            interp2<S>(ysrc, base, wl, aC, aR);
         }
         // b: (t, phi)
-        const double phi = fma(thcj, thi, thj), phic = thcj * thci;
+        const double phi = fma(thcj, thi, thj);
         double bC, bR;
         {
-            const double x = xmap(a, phi, phic);
-            const int base = lagrange<S>(x, L, wl);
-            interp2<S>(a.y, base, wl, bC, bR);
+            const int base = lagrange<S>(double(L - 1) - Xb[L - 1 - i], L, wl);
+            interp2<S>(ysrc, base, wl, bC, bR);
         }
         // c: (t', theta_i)
         double cC, cR;
-        if (cmode == 0) {
-            const YPoint v = a.y[i];
-            cC = v.c;
-            cR = v.r;
+        if (cmode == 2) {
+            const HP v0 = c0p[i], v1 = c1p[i];
+            cC = double(cw0 * v0.c + cw1 * v0.dc + cw2 * v1.c + cw3 * v1.dc);
+            cR = double(cw0 * v0.r + cw1 * v0.dr + cw2 * v1.r + cw3 * v1.dr);
+        } else if (cmode == 3) {
+            const HP v0 = c0p[i];
+            const YPoint yc = ysrc[i];
+            cC = double(cw0 * v0.c + cw1 * v0.dc) + double(cw2) * yc.c;
+            cR = double(cw0 * v0.r + cw1 * v0.dr) + double(cw2) * yc.r;
         } else if (cmode == 1) {
-            const HPoint v = c0p[i];
+            const HP v = c0p[i];
+            cC = double(v.c);
+            cR = double(v.r);
+        } else {
+            const YPoint v = ysrc[i];
             cC = v.c;
             cR = v.r;
-        } else if (cmode == 2) {
-            const HPoint v0 = c0p[i], v1 = c1p[i];
-            cC = cw0 * v0.c + cw1 * v0.dc + cw2 * v1.c + cw3 * v1.dc;
-            cR = cw0 * v0.r + cw1 * v0.dr + cw2 * v1.r + cw3 * v1.dr;
-        } else {
-            const HPoint v0 = c0p[i];
-            const YPoint yc = a.y[i];
-            cC = cw0 * v0.c + cw1 * v0.dc + cw2 * yc.c;
-            cR = cw0 * v0.r + cw1 * v0.dr + cw2 * yc.r;
         }
         if (i == 0) c0C = cC;
         // d: (phi t, psi)
         double dC, dR;
         {
-            double psi = 0.0, psic = 1.0;  // psi = 0/0 := 0 at i = j = 0
-            if (phi > 0.0) {
-                psi = thj / phi;
-                psic = thcj * thi / phi;
-            }
-            const double x = xmap(a, psi, psic);
-            const int base = lagrange<S>(x, L, wl);
+            HR wd[S];
+            const int base = lagrange<S, HR>(Xdj[i], L, wd);
             const double s = phi * t;
             if (nb == 0) {
-                interp2<S>(a.y, base, wl, dC, dR);
+                double wy[S];
+#pragma unroll
+                for (int k = 0; k < S; ++k) wy[k] = double(wd[k]);
+                interp2<S>(ysrc, base, wy, dC, dR);
             } else if (s <= tb) {
                 if (b == 0) {
-                    interp2h<S>(slot0, base, wl, dC, dR);
+                    HR c, r;
+                    interp2h<S>(slot0, base, wd, c, r);
+                    dC = double(c);
+                    dR = double(r);
                 } else {
-                    const int m = bracket(s_t, lo, b, s);
-                    lo = m;
+                    const int m = bracket_fast(s_t, s_bk, B, b, s);
                     const double h = s_t[m + 1] - s_t[m];
                     const double u = (s - s_t[m]) / h;
-                    HPoint p0, p1;
-                    interp4<S>(a.hist + size_t(a.slot[m]) * L, base, wl, p0);
-                    interp4<S>(a.hist + size_t(a.slot[m + 1]) * L, base, wl, p1);
-                    const double h00 = 2 * u * u * u - 3 * u * u + 1, h10 = (u * u * u - 2 * u * u + u) * h;
-                    const double h01 = -2 * u * u * u + 3 * u * u, h11 = (u * u * u - u * u) * h;
-                    dC = h00 * p0.c + h10 * p0.dc + h01 * p1.c + h11 * p1.dc;
-                    dR = h00 * p0.r + h10 * p0.dr + h01 * p1.r + h11 * p1.dr;
+                    HR c0, r0, dc0, dr0, c1, r1, dc1, dr1;
+                    interp4<S>(hist + size_t(a.slot[m]) * L, base, wd, c0, r0, dc0, dr0);
+                    __builtin_amdgcn_sched_barrier(0);  // bound the gathers in flight (registers)
+                    interp4<S>(hist + size_t(a.slot[m + 1]) * L, base, wd, c1, r1, dc1, dr1);
+                    const HR h00 = HR(2 * u * u * u - 3 * u * u + 1), h10 = HR((u * u * u - 2 * u * u + u) * h);
+                    const HR h01 = HR(-2 * u * u * u + 3 * u * u), h11 = HR((u * u * u - u * u) * h);
+                    dC = double(h00 * c0 + h10 * dc0 + h01 * c1 + h11 * dc1);
+                    dR = double(h00 * r0 + h10 * dr0 + h01 * r1 + h11 * dr1);
                 }
             } else {
-                HPoint pb;
-                interp4<S>(bslot, base, wl, pb);
+                HR pc, pr, pdc, pdr;
+                interp4<S>(bslot, base, wd, pc, pr, pdc, pdr);
+                double wy[S];
+#pragma unroll
+                for (int k = 0; k < S; ++k) wy[k] = double(wd[k]);
                 double yc, yr;
-                interp2<S>(a.y, base, wl, yc, yr);
+                interp2<S>(ysrc, base, wy, yc, yr);
                 const double u = (s - tb) / hq;
                 const double q0 = 1.0 - u * u, q1 = hq * (u - u * u), q2 = u * u;
-                dC = q0 * pb.c + q1 * pb.dc + q2 * yc;
-                dR = q0 * pb.r + q1 * pb.dr + q2 * yr;
+                dC = q0 * double(pc) + q1 * double(pdc) + q2 * yc;
+                dR = q0 * double(pr) + q1 * double(pdr) + q2 * yr;
             }
         }
         const double f2a = fD2<PM>(a.m, aC), f1a = fD1<PM>(a.m, aC);
@@ -346,10 +468,34 @@ __global__ __launch_bounds__(256) void k_hist_integral(const StageArgs a) {
         }
         a.kout[j] = YPoint{oc, orr};
         if (a.store) {
-            a.store[j].dc = oc;
-            a.store[j].dr = orr;
+            HP* st = static_cast<HP*>(a.store);
+            st[j].dc = HR(oc);
+            st[j].dr = HR(orr);
         }
     }
+}
+
+// One instance: the stage arguments travel by value.
+template <int S, int PM, class HP, bool YL>
+__global__ __launch_bounds__(kRowsPerBlock * 64) void k_hist_integral(const StageArgs a) {
+    hist_integral_block<S, PM, HP, YL>(a, blockIdx.x);
+}
+
+// Many instances in one launch (serving): block b belongs to the instance q
+// with first_block[q] <= b < first_block[q+1]; instances may differ in L, M,
+// t and history.  The dynamic LDS is sized for the largest nb of the batch.
+template <int S, int PM, class HP, bool YL>
+__global__ __launch_bounds__(kRowsPerBlock * 64) void k_hist_integral_multi(const StageArgs* __restrict__ args,
+                                                                            const int* __restrict__ first_block,
+                                                                            int n_inst) {
+    int lo = 0, hi = n_inst;  // first_block[lo] <= b < first_block[hi]
+    const int b = blockIdx.x;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (first_block[mid] <= b) lo = mid;
+        else hi = mid;
+    }
+    hist_integral_block<S, PM, HP, YL>(args[lo], b - first_block[lo]);
 }
 
 // ---------------------------------------------------------------- RK stage combinations
@@ -358,13 +504,13 @@ struct Coef10 {
 };
 
 // ys = y0 + dt sum_{l < nk} a_l k_l; the diagonal point is pinned to (1, 1).
-__global__ void k_rk_combine(int L, const YPoint* __restrict__ y0, const YPoint* __restrict__ k, int nk,
-                             const Coef10 a, double dt, YPoint* __restrict__ ys) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void rk_combine_point(int i, int L, const YPoint* __restrict__ y0,
+                                                 const YPoint* __restrict__ k, int nk, const double* a, double dt,
+                                                 YPoint* __restrict__ ys) {
     if (i >= L) return;
     YPoint acc = y0[i];
     for (int l = 0; l < nk; ++l) {
-        const double f = dt * a.v[l];
+        const double f = dt * a[l];
         const YPoint kv = k[size_t(l) * L + i];
         acc.c = fma(f, kv.c, acc.c);
         acc.r = fma(f, kv.r, acc.r);
@@ -372,13 +518,28 @@ __global__ void k_rk_combine(int L, const YPoint* __restrict__ y0, const YPoint*
     if (i == L - 1) acc = YPoint{1.0, 1.0};
     ys[i] = acc;
 }
+__global__ void k_rk_combine(int L, const YPoint* __restrict__ y0, const YPoint* __restrict__ k, int nk,
+                             const Coef10 a, double dt, YPoint* __restrict__ ys) {
+    rk_combine_point(blockIdx.x * blockDim.x + threadIdx.x, L, y0, k, nk, a.v, dt, ys);
+}
+__global__ __launch_bounds__(kCombineBlock) void k_rk_combine_multi(const CombineDesc* __restrict__ d,
+                                                                    const int* __restrict__ first_block, int n) {
+    int lo = 0, hi = n;
+    const int b = blockIdx.x;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (first_block[mid] <= b) lo = mid;
+        else hi = mid;
+    }
+    const CombineDesc& q = d[lo];
+    rk_combine_point((b - first_block[lo]) * blockDim.x + threadIdx.x, q.L, q.y0, q.k, q.nk, q.a, q.dt, q.ys);
+}
 
 // ynew = y0 + dt sum b_l k_l and eps = sum_i |dt sum e_l k_l| over both fields
 // (Sec. 3.5), one block so that the sum has a fixed order.
-__global__ __launch_bounds__(1024) void k_rk_finish(int L, const YPoint* __restrict__ y0,
-                                                    const YPoint* __restrict__ k, int nk, const Coef10 bw,
-                                                    const Coef10 ew, double dt, YPoint* __restrict__ ynew,
-                                                    double* __restrict__ eps_out) {
+__device__ __forceinline__ void rk_finish_body(int L, const YPoint* __restrict__ y0, const YPoint* __restrict__ k,
+                                               int nk, const double* bw, const double* ew, double dt,
+                                               YPoint* __restrict__ ynew, double* __restrict__ eps_out) {
     __shared__ double sh[16];
     double sum = 0.0;
     for (int i = threadIdx.x; i < L; i += blockDim.x) {
@@ -386,11 +547,11 @@ __global__ __launch_bounds__(1024) void k_rk_finish(int L, const YPoint* __restr
         double ec = 0.0, er = 0.0;
         for (int l = 0; l < nk; ++l) {
             const YPoint kv = k[size_t(l) * L + i];
-            const double f = dt * bw.v[l];
+            const double f = dt * bw[l];
             acc.c = fma(f, kv.c, acc.c);
             acc.r = fma(f, kv.r, acc.r);
-            ec = fma(ew.v[l], kv.c, ec);
-            er = fma(ew.v[l], kv.r, er);
+            ec = fma(ew[l], kv.c, ec);
+            er = fma(ew[l], kv.r, er);
         }
         if (i == L - 1) acc = YPoint{1.0, 1.0};
         ynew[i] = acc;
@@ -399,39 +560,55 @@ __global__ __launch_bounds__(1024) void k_rk_finish(int L, const YPoint* __restr
     sum = block_sum(sum, sh);
     if (threadIdx.x == 0) eps_out[0] = sum;
 }
-
-__global__ void k_append(int L, const YPoint* __restrict__ y, HPoint* __restrict__ dst) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= L) return;
-    dst[i].c = y[i].c;
-    dst[i].r = y[i].r;
+__global__ __launch_bounds__(1024) void k_rk_finish(int L, const YPoint* __restrict__ y0,
+                                                    const YPoint* __restrict__ k, int nk, const Coef10 bw,
+                                                    const Coef10 ew, double dt, YPoint* __restrict__ ynew,
+                                                    double* __restrict__ eps_out) {
+    rk_finish_body(L, y0, k, nk, bw.v, ew.v, dt, ynew, eps_out);
+}
+__global__ __launch_bounds__(1024) void k_rk_finish_multi(const FinishDesc* __restrict__ d) {
+    const FinishDesc& q = d[blockIdx.x];
+    rk_finish_body(q.L, q.y0, q.k, q.nk, q.b, q.e, q.dt, q.ynew, q.eps);
 }
 
-__global__ void k_load_state(int L, const HPoint* __restrict__ src, YPoint* __restrict__ y) {
+template <class HP>
+__global__ void k_append(int L, const YPoint* __restrict__ y, HP* __restrict__ dst) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= L) return;
-    y[i] = YPoint{src[i].c, src[i].r};
+    dst[i].c = hreal_t<HP>(y[i].c);
+    dst[i].r = hreal_t<HP>(y[i].r);
+}
+
+template <class HP>
+__global__ void k_load_state(int L, const HP* __restrict__ src, YPoint* __restrict__ y) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= L) return;
+    y[i] = YPoint{double(src[i].c), double(src[i].r)};
 }
 
 // ---------------------------------------------------------------- sparsification residual
+__device__ __forceinline__ HPoint up(const HPoint& v) { return v; }
+__device__ __forceinline__ HPoint up(const HPoint32& v) {
+    return HPoint{double(v.c), double(v.r), double(v.dc), double(v.dr)};
+}
 // eps_n = sum_i |Delta^C_n(theta_i)| + |Delta^R_n(theta_i)| with Delta the Hermite
 // integral over [t_{n-1}, t_{n+1}] with slice n minus the one without (Sec. 3.6).
 __device__ __forceinline__ double herm_int(double h, double ya, double da, double yb, double db) {
     return h * (ya + yb) * 0.5 + h * h * (da - db) * (1.0 / 12.0);
 }
+template <class HP>
 __global__ __launch_bounds__(256) void k_sparsify_residual(int L, int first, const double* __restrict__ thist,
-                                                           const int* __restrict__ slot,
-                                                           const HPoint* __restrict__ hist,
+                                                           const int* __restrict__ slot, const HP* __restrict__ hist,
                                                            double* __restrict__ eps_n) {
     __shared__ double sh[16];
     const int n = first + blockIdx.x;
-    const HPoint* pa = hist + size_t(slot[n - 1]) * L;
-    const HPoint* pc = hist + size_t(slot[n]) * L;
-    const HPoint* pb = hist + size_t(slot[n + 1]) * L;
+    const HP* pa = hist + size_t(slot[n - 1]) * L;
+    const HP* pc = hist + size_t(slot[n]) * L;
+    const HP* pb = hist + size_t(slot[n + 1]) * L;
     const double h1 = thist[n] - thist[n - 1], h2 = thist[n + 1] - thist[n], h3 = thist[n + 1] - thist[n - 1];
     double e = 0.0;
     for (int i = threadIdx.x; i < L; i += blockDim.x) {
-        const HPoint va = pa[i], vc = pc[i], vb = pb[i];
+        const HPoint va = up(pa[i]), vc = up(pc[i]), vb = up(pb[i]);
         const double dc = herm_int(h1, va.c, va.dc, vc.c, vc.dc) + herm_int(h2, vc.c, vc.dc, vb.c, vb.dc) -
                           herm_int(h3, va.c, va.dc, vb.c, vb.dc);
         const double dr = herm_int(h1, va.r, va.dr, vc.r, vc.dr) + herm_int(h2, vc.r, vc.dr, vb.r, vb.dr) -
@@ -443,18 +620,17 @@ __global__ __launch_bounds__(256) void k_sparsify_residual(int L, int first, con
 }
 
 // ---------------------------------------------------------------- observables and copies
-template <int PM>
+template <int PM, class HP>
 __global__ __launch_bounds__(256) void k_slice_observables(const Model m, int L, const double* __restrict__ nu,
                                                            const double* __restrict__ thist,
-                                                           const int* __restrict__ slot,
-                                                           const HPoint* __restrict__ hist, double* __restrict__ E,
-                                                           double* __restrict__ mu) {
+                                                           const int* __restrict__ slot, const HP* __restrict__ hist,
+                                                           double* __restrict__ E, double* __restrict__ mu) {
     __shared__ double sh[16];
     const int n = blockIdx.x;
-    const HPoint* p = hist + size_t(slot[n]) * L;
+    const HP* p = hist + size_t(slot[n]) * L;
     double sk = 0.0, se = 0.0;
     for (int i = threadIdx.x; i < L; i += blockDim.x) {
-        const HPoint v = p[i];
+        const HPoint v = up(p[i]);
         const double d1 = fD1<PM>(m, v.c), d2 = fD2<PM>(m, v.c);
         sk = fma(nu[i], d2 * v.r * v.c + d1 * v.r, sk);
         se = fma(nu[i], d1 * v.r, se);
@@ -463,28 +639,31 @@ __global__ __launch_bounds__(256) void k_slice_observables(const Model m, int L,
     se = block_sum(se, sh);
     if (threadIdx.x == 0) {
         const double t = thist[n];
-        const double c0 = p[0].c;
+        const double c0 = double(p[0].c);
         if (mu) mu[n] = m.T + t * sk + m.beta0 * fD1<PM>(m, c0) * c0;
         if (E) E[n] = -t * se - m.beta0 * fF<PM>(m, c0);
     }
 }
 
-__global__ void k_pack(int L, int count, int field, const int* __restrict__ slot, const HPoint* __restrict__ hist,
+template <class HP>
+__global__ void k_pack(int L, int count, int field, const int* __restrict__ slot, const HP* __restrict__ hist,
                        double* __restrict__ dst) {
     const size_t idx = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (idx >= size_t(count) * L) return;
     const int n = int(idx / L), i = int(idx % L);
-    const HPoint v = hist[size_t(slot[n]) * L + i];
+    const HPoint v = up(hist[size_t(slot[n]) * L + i]);
     dst[idx] = field == 0 ? v.c : field == 1 ? v.r : field == 2 ? v.dc : v.dr;
 }
 
+template <class HP>
 __global__ void k_unpack(int L, int count, const double* __restrict__ C, const double* __restrict__ R,
                          const double* __restrict__ dC, const double* __restrict__ dR,
-                         const int* __restrict__ slot, HPoint* __restrict__ hist) {
+                         const int* __restrict__ slot, HP* __restrict__ hist) {
     const size_t idx = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (idx >= size_t(count) * L) return;
     const int n = int(idx / L), i = int(idx % L);
-    hist[size_t(slot[n]) * L + i] = HPoint{C[idx], R[idx], dC[idx], dR[idx]};
+    using R_ = hreal_t<HP>;
+    hist[size_t(slot[n]) * L + i] = HP{R_(C[idx]), R_(R[idx]), R_(dC[idx]), R_(dR[idx])};
 }
 
 __global__ void k_interleave(int L, const double* __restrict__ a, const double* __restrict__ b,
@@ -505,6 +684,11 @@ inline unsigned nblk(size_t n, unsigned bs) { return unsigned((n + bs - 1) / bs)
 }  // namespace
 
 // ---------------------------------------------------------------- launchers
+hipError_t launch_coords(const GridArgs& g, hipStream_t st) {
+    hipLaunchKernelGGL(k_coords, dim3(nblk(g.L, 256), g.L), dim3(256), 0, st, g);
+    return hipGetLastError();
+}
+
 hipError_t launch_stage_prep(const Model& m, int L, double t, const double* nu, const YPoint* y, double* mue,
                              hipStream_t st) {
     if (m.pmax <= 4) hipLaunchKernelGGL(k_stage_prep<4>, dim3(1), dim3(1024), 0, st, m, L, t, nu, y, mue);
@@ -512,14 +696,47 @@ hipError_t launch_stage_prep(const Model& m, int L, double t, const double* nu, 
     return hipGetLastError();
 }
 
+// Largest dynamic LDS a block may use on this device (queried once).
+static size_t max_lds() {
+    static size_t v = 0;
+    if (v == 0) {
+        int dev = 0, b = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&b, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && b > 0)
+            v = size_t(b);
+        else
+            v = 65536;
+    }
+    return v;
+}
+
+template <class K>
+static void allow_lds(K kernel, size_t bytes) {
+    if (bytes > 65536) (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
+}
+
+template <int S, class HP, bool YL>
+static void launch_hi_shy(const StageArgs& a, size_t lds, hipStream_t st) {
+    const dim3 grid(nblk(a.L, kRowsPerBlock)), block(kRowsPerBlock * kWave);
+    if (a.m.pmax <= 4) {
+        allow_lds(k_hist_integral<S, 4, HP, YL>, lds);
+        hipLaunchKernelGGL((k_hist_integral<S, 4, HP, YL>), grid, block, lds, st, a);
+    } else {
+        allow_lds(k_hist_integral<S, DMFE_MAX_P, HP, YL>, lds);
+        hipLaunchKernelGGL((k_hist_integral<S, DMFE_MAX_P, HP, YL>), grid, block, lds, st, a);
+    }
+}
+template <int S, class HP>
+static hipError_t launch_hi_sh(const StageArgs& a, hipStream_t st) {
+    const size_t with_y = lds_bytes(a.nb, a.L, true);
+    if (with_y <= max_lds()) launch_hi_shy<S, HP, true>(a, with_y, st);
+    else launch_hi_shy<S, HP, false>(a, lds_bytes(a.nb, a.L, false), st);
+    return hipGetLastError();
+}
 template <int S>
 static hipError_t launch_hi_s(const StageArgs& a, hipStream_t st) {
-    const unsigned rows_per_block = 4;
-    const dim3 grid(nblk(a.L, rows_per_block)), block(rows_per_block * kWave);
-    const size_t lds = size_t(a.nb > 0 ? a.nb : 1) * sizeof(double);
-    if (a.m.pmax <= 4) hipLaunchKernelGGL((k_hist_integral<S, 4>), grid, block, lds, st, a);
-    else hipLaunchKernelGGL((k_hist_integral<S, DMFE_MAX_P>), grid, block, lds, st, a);
-    return hipGetLastError();
+    return a.fp32 ? launch_hi_sh<S, HPoint32>(a, st) : launch_hi_sh<S, HPoint>(a, st);
 }
 
 hipError_t launch_hist_integral(const StageArgs& a, int s, hipStream_t st) {
@@ -552,47 +769,80 @@ hipError_t launch_rk_finish(int L, const YPoint* y0, const YPoint* k, int nk, co
     return hipGetLastError();
 }
 
-hipError_t launch_append(int L, const YPoint* y, HPoint* slot_dst, hipStream_t st) {
-    hipLaunchKernelGGL(k_append, dim3(nblk(L, 256)), dim3(256), 0, st, L, y, slot_dst);
+hipError_t launch_append(int L, const YPoint* y, void* slot_dst, int fp32, hipStream_t st) {
+    if (fp32)
+        hipLaunchKernelGGL(k_append<HPoint32>, dim3(nblk(L, 256)), dim3(256), 0, st, L, y,
+                           static_cast<HPoint32*>(slot_dst));
+    else
+        hipLaunchKernelGGL(k_append<HPoint>, dim3(nblk(L, 256)), dim3(256), 0, st, L, y, static_cast<HPoint*>(slot_dst));
     return hipGetLastError();
 }
 
-hipError_t launch_load_state(int L, const HPoint* slot_src, YPoint* y, hipStream_t st) {
-    hipLaunchKernelGGL(k_load_state, dim3(nblk(L, 256)), dim3(256), 0, st, L, slot_src, y);
+hipError_t launch_load_state(int L, const void* slot_src, int fp32, YPoint* y, hipStream_t st) {
+    if (fp32)
+        hipLaunchKernelGGL(k_load_state<HPoint32>, dim3(nblk(L, 256)), dim3(256), 0, st, L,
+                           static_cast<const HPoint32*>(slot_src), y);
+    else
+        hipLaunchKernelGGL(k_load_state<HPoint>, dim3(nblk(L, 256)), dim3(256), 0, st, L,
+                           static_cast<const HPoint*>(slot_src), y);
     return hipGetLastError();
 }
 
 hipError_t launch_sparsify_residual(int L, int first, int count, const double* thist, const int* slot,
-                                    const HPoint* hist, double* eps_n, hipStream_t st) {
+                                    const void* hist, int fp32, double* eps_n, hipStream_t st) {
     if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_sparsify_residual, dim3(count), dim3(256), 0, st, L, first, thist, slot, hist, eps_n);
+    if (fp32)
+        hipLaunchKernelGGL(k_sparsify_residual<HPoint32>, dim3(count), dim3(256), 0, st, L, first, thist, slot,
+                           static_cast<const HPoint32*>(hist), eps_n);
+    else
+        hipLaunchKernelGGL(k_sparsify_residual<HPoint>, dim3(count), dim3(256), 0, st, L, first, thist, slot,
+                           static_cast<const HPoint*>(hist), eps_n);
     return hipGetLastError();
+}
+
+template <class HP>
+static void obs_launch(const Model& m, int L, const double* nu, int count, const double* thist, const int* slot,
+                       const HP* hist, double* E, double* mu, hipStream_t st) {
+    if (m.pmax <= 4)
+        hipLaunchKernelGGL((k_slice_observables<4, HP>), dim3(count), dim3(256), 0, st, m, L, nu, thist, slot, hist, E,
+                           mu);
+    else
+        hipLaunchKernelGGL((k_slice_observables<DMFE_MAX_P, HP>), dim3(count), dim3(256), 0, st, m, L, nu, thist, slot,
+                           hist, E, mu);
 }
 
 hipError_t launch_slice_observables(const Model& m, int L, const double* nu, int count, const double* thist,
-                                    const int* slot, const HPoint* hist, double* E, double* mu, hipStream_t st) {
+                                    const int* slot, const void* hist, int fp32, double* E, double* mu,
+                                    hipStream_t st) {
     if (count <= 0) return hipSuccess;
-    if (m.pmax <= 4)
-        hipLaunchKernelGGL(k_slice_observables<4>, dim3(count), dim3(256), 0, st, m, L, nu, thist, slot, hist, E, mu);
-    else
-        hipLaunchKernelGGL(k_slice_observables<DMFE_MAX_P>, dim3(count), dim3(256), 0, st, m, L, nu, thist, slot,
-                           hist, E, mu);
+    if (fp32) obs_launch(m, L, nu, count, thist, slot, static_cast<const HPoint32*>(hist), E, mu, st);
+    else obs_launch(m, L, nu, count, thist, slot, static_cast<const HPoint*>(hist), E, mu, st);
     return hipGetLastError();
 }
 
-hipError_t launch_pack_history(int L, int count, int field, const int* slot, const HPoint* hist, double* dst,
-                               hipStream_t st) {
+hipError_t launch_pack_history(int L, int count, int field, const int* slot, const void* hist, int fp32,
+                               double* dst, hipStream_t st) {
     if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_pack, dim3(nblk(size_t(count) * L, 256)), dim3(256), 0, st, L, count, field, slot, hist,
-                       dst);
+    const dim3 g(nblk(size_t(count) * L, 256));
+    if (fp32)
+        hipLaunchKernelGGL(k_pack<HPoint32>, g, dim3(256), 0, st, L, count, field, slot,
+                           static_cast<const HPoint32*>(hist), dst);
+    else
+        hipLaunchKernelGGL(k_pack<HPoint>, g, dim3(256), 0, st, L, count, field, slot, static_cast<const HPoint*>(hist),
+                           dst);
     return hipGetLastError();
 }
 
 hipError_t launch_unpack_history(int L, int count, const double* C, const double* R, const double* dC,
-                                 const double* dR, const int* slot, HPoint* hist, hipStream_t st) {
+                                 const double* dR, const int* slot, void* hist, int fp32, hipStream_t st) {
     if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_unpack, dim3(nblk(size_t(count) * L, 256)), dim3(256), 0, st, L, count, C, R, dC, dR, slot,
-                       hist);
+    const dim3 g(nblk(size_t(count) * L, 256));
+    if (fp32)
+        hipLaunchKernelGGL(k_unpack<HPoint32>, g, dim3(256), 0, st, L, count, C, R, dC, dR, slot,
+                           static_cast<HPoint32*>(hist));
+    else
+        hipLaunchKernelGGL(k_unpack<HPoint>, g, dim3(256), 0, st, L, count, C, R, dC, dR, slot,
+                           static_cast<HPoint*>(hist));
     return hipGetLastError();
 }
 
@@ -603,6 +853,49 @@ hipError_t launch_interleave(int L, const double* a, const double* b, YPoint* y,
 
 hipError_t launch_deinterleave(int L, const YPoint* y, double* a, double* b, hipStream_t st) {
     hipLaunchKernelGGL(k_deinterleave, dim3(nblk(L, 256)), dim3(256), 0, st, L, y, a, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_rk_combine_multi(const CombineDesc* d, const int* first_block, int n, int total_blocks,
+                                   hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rk_combine_multi, dim3(total_blocks), dim3(kCombineBlock), 0, st, d, first_block, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_stage_prep_multi(const PrepDesc* d, int n, int pmax, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    if (pmax <= 4) hipLaunchKernelGGL(k_stage_prep_multi<4>, dim3(n), dim3(1024), 0, st, d);
+    else hipLaunchKernelGGL(k_stage_prep_multi<DMFE_MAX_P>, dim3(n), dim3(1024), 0, st, d);
+    return hipGetLastError();
+}
+
+template <int S, class HP>
+static void hist_multi_launch(const StageArgs* d, const int* fb, int n, int blocks, int pmax, size_t lds,
+                              hipStream_t st) {
+    allow_lds(k_hist_integral_multi<S, 4, HP, false>, lds);
+    allow_lds(k_hist_integral_multi<S, DMFE_MAX_P, HP, false>, lds);
+    if (pmax <= 4)
+        hipLaunchKernelGGL((k_hist_integral_multi<S, 4, HP, false>), dim3(blocks), dim3(kRowsPerBlock * kWave), lds,
+                           st, d, fb, n);
+    else
+        hipLaunchKernelGGL((k_hist_integral_multi<S, DMFE_MAX_P, HP, false>), dim3(blocks),
+                           dim3(kRowsPerBlock * kWave), lds, st, d, fb, n);
+}
+
+hipError_t launch_hist_integral_multi(const StageArgs* d, const int* first_block, int n, int total_blocks, int s,
+                                      int pmax, int fp32, int nb_max, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const size_t lds = lds_bytes(nb_max, 0, false);
+    if (s != 10) return hipErrorInvalidValue;  // the pool serves the default stencil
+    if (fp32) hist_multi_launch<10, HPoint32>(d, first_block, n, total_blocks, pmax, lds, st);
+    else hist_multi_launch<10, HPoint>(d, first_block, n, total_blocks, pmax, lds, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_rk_finish_multi(const FinishDesc* d, int n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rk_finish_multi, dim3(n), dim3(1024), 0, st, d);
     return hipGetLastError();
 }
 

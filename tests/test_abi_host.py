@@ -157,6 +157,9 @@ def test_sparsify_select_matches_oracle(lib):
 def test_footprint(lib):
     p = pk.make_params({3: 0.5, 4: 0.5}, 0.55, t_max=1e7, L=4096)
     fp = pk.dmfe_footprint(p)
-    assert 4096 * 4096 * 32 <= fp < 4096 * 4096 * 32 * 1.01
+    hist, coords = 4096 * 4096 * 32, 2 * 4096 * 4096 * 8  # history slots + the two coordinate tables
+    assert hist + coords <= fp < (hist + coords) * 1.01
+    p32 = pk.make_params({3: 0.5, 4: 0.5}, 0.55, t_max=1e7, L=4096, precision=pk.FP32_COMP)
+    assert fp - pk.dmfe_footprint(p32) == hist // 2
     pu = pk.make_params({3: 1.0}, 0.5, mode=pk.UNIFORM, h=0.05, N=1000)
     assert pk.dmfe_footprint(pu) >= 2 * 1001 * 1002 // 2 * 8

@@ -1,0 +1,84 @@
+"""Serving pool: solves stepped together in batched launches give the same results
+as the same solves run alone, admission respects the memory arena, and requests
+submitted while others run are admitted as memory frees up."""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+import paper_2604_06309_amd as pk  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _requests(n, seed=5):
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n):
+        a2 = rng.dirichlet([1.0, 1.0, 1.0])
+        L = int(rng.choice([64, 96, 128]))
+        p = pk.make_params({2: a2[0], 3: a2[1], 4: a2[2]}, float(rng.uniform(0.4, 1.2)),
+                           t_max=float(np.exp(rng.uniform(np.log(4.0), np.log(8.0)))), L=L, M_cap=1500,
+                           eps=1e-7, dt0=1e-3, dt_min=1e-10)
+        out.append(p)
+    return out
+
+
+def _solo(p):
+    s = pk.Solver(p)
+    st, info = s.step(float("inf"))
+    res = (s.read(pk.F_T_GRID), s.read(pk.F_C), s.read(pk.F_R), info.accepted, info.rejected)
+    s.close()
+    return res
+
+
+def test_pool_matches_solo_runs_and_admits_by_memory():
+    say("pool vs solo")
+    reqs = _requests(10)
+    solo = [_solo(p) for p in reqs]
+    fp = max(pk.dmfe_footprint(p) for p in reqs)
+    arena = 3 * fp + 4096  # at most three solves resident at a time
+    pool = pk.Pool(arena, max_instances=8)
+    ids = [pool.submit(p) for p in reqs[:6]]
+    st = pool.run(50)
+    assert st.running <= 3 and st.running + st.queued + st.finished_unreleased >= 1
+    ids += [pool.submit(p) for p in reqs[6:]]  # arrive while others run
+    done = {}
+    for _ in range(100000):
+        st = pool.run(200)
+        for rid in pool.poll():
+            info, tm = pool.result(rid)
+            k = ids.index(rid)
+            assert tm.status == pk.DONE, (rid, tm.status)
+            L = reqs[k].L
+            done[rid] = (pool.read(rid, pk.F_T_GRID), pool.read(rid, pk.F_C, L=L), pool.read(rid, pk.F_R, L=L),
+                         info.accepted, info.rejected, tm.total_s)
+            pool.release(rid)
+        assert st.running <= 3
+        if len(done) == len(reqs):
+            break
+    assert len(done) == len(reqs)
+    for k, rid in enumerate(ids):
+        t, C, R, acc, rej, tts = done[rid]
+        t0, C0, R0, acc0, rej0 = solo[k]
+        assert (acc, rej) == (acc0, rej0)
+        np.testing.assert_array_equal(t, t0)
+        np.testing.assert_array_equal(C, C0)
+        np.testing.assert_array_equal(R, R0)
+    say(f"  {len(reqs)} solves identical to solo runs; ticks={st.ticks}")
+    pool.close()
+
+
+def test_pool_rejects_what_cannot_fit():
+    p = _requests(1)[0]
+    pool = pk.Pool(pk.dmfe_footprint(p) // 2, max_instances=2)
+    with pytest.raises(pk.DmfeError) as e:
+        pool.submit(p)
+    assert e.value.status == pk.ERR_NOMEM
+    pool.close()

@@ -33,16 +33,49 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def calibration_copies(torch, nbytes: int = 256 << 20, reps: int = 2):
+    """Plain device copies of known size (a blit and an elementwise kernel that
+    read and write nbytes each), run right after the timed launches so that
+    hardware byte counters of a profiled run can be scaled to bytes."""
+    src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").uniform_()
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+        torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    return {"bytes_read": nbytes, "bytes_written": nbytes, "reps": reps}
+
+
+def traffic_record(L: int, precision: str):
+    """HBM bytes per launch of the history-integral kernel, from the committed
+    counter summary, if it was taken on the kernel source as it is now."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"hist_integral_L{L}_{precision}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            rec[k.strip()] = v.strip()
+    src = os.path.join(ROOT, "paper_2604_06309_amd", "csrc", "kernels_theta.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if rec.get("kernel_source_sha256") != sha:
+        return None
+    return float(rec["traffic_bytes_per_launch"])
+
+
 def workload_params(pk, precision):
     return pk.make_params({3: 0.5, 4: 0.5}, 0.55, t_max=1e7, L=4096, M_cap=4096, eps=1e-8, dt0=1e-3,
                           dt_min=1e-12, precision=precision)
 
 
-def hist_integral_bytes(L: int, slices: float) -> float:
+def hist_integral_bytes(L: int, slices: float, fp32: bool = False) -> float:
     """Algorithmic bytes of one history-integral launch: every stored point of
-    the slices with a derivative (4 doubles) once, the stage slice and the
-    output (2 doubles each per grid point) and theta, 1-theta, nu."""
-    return slices * L * 32.0 + L * (16.0 + 16.0 + 24.0)
+    the slices (C, R, dC/dt, dR/dt: 32 bytes in FP64, 16 in FP32) once, the
+    stage slice and the output (2 doubles each per grid point) and theta,
+    1-theta, nu."""
+    return slices * L * (16.0 if fp32 else 32.0) + L * (16.0 + 16.0 + 24.0)
 
 
 def cpu_baseline(L: int, M: int, evals_per_step: float, budget_s: float = 20.0):
@@ -167,6 +200,49 @@ def serving_sweep(pk, n: int = 24, seed: int = 20260406):
     return out
 
 
+def kernel_bench(pk, args) -> dict:
+    """The history-integral kernel alone at the workload's full size: a seeded
+    smooth synthetic history of M slices at geometrically spaced times up to
+    t = 200 and a stage at t = 200.08, the time and step of the solver's own
+    steady state on this workload (the shared input generator of the tests),
+    one right-hand-side evaluation per step.  A plain device copy of known size runs beside it, so hardware
+    byte counters of the kernel can be calibrated against the copy."""
+    import numpy as np
+    import torch
+
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import inputs
+
+    prec = pk.FP64 if args.precision == "fp64" else pk.FP32_COMP
+    L, M = 4096, args.kernel_slices
+    params = pk.make_params({3: 0.5, 4: 0.5}, 0.55, t_max=1e7, L=L, M_cap=M, eps=1e-8, dt0=1e-3, dt_min=1e-12,
+                            precision=prec)
+    s = pk.Solver(params)
+    th = s.read(pk.F_THETA)
+    t_last, t = 200.0, 200.08
+    times = inputs.geometric_times(M, t_last, t_first=0.01)
+    C, R, dC, dR = inputs.smooth_history(th, times, 1)
+    s.set_history(times, C, R, dC, dR)
+    del C, R, dC, dR
+    yC, yR = inputs.smooth_stage(th, t, 1)
+    yC, yR = torch.tensor(yC, device="cuda"), torch.tensor(yR, device="cuda")
+    for _ in range(args.warmup):
+        s.rhs(t, yC, yR, M)
+    s.timing(True)
+    for _ in range(args.steps):
+        s.rhs(t, yC, yR, M)
+    torch.cuda.synchronize()
+    n, ms, slices = s.timing_read(pk.K_HIST_INTEGRAL)
+    s.timing(False)
+    s.close()
+    cal = calibration_copies(torch)
+    avg_us = ms / n * 1e3
+    alg = hist_integral_bytes(L, slices / n, fp32=prec == pk.FP32_COMP)
+    return {"kernel": "hist_integral", "L": L, "M": M, "precision": args.precision, "launches": n,
+            "avg_launch_us": avg_us, "algorithmic_bytes_per_launch": alg,
+            "achieved_GBps": alg / (avg_us * 1e-6) / 1e9, "calibration_copies": cal}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -176,6 +252,10 @@ def main() -> int:
     ap.add_argument("--fill-seconds", type=float, default=150.0, help="time budget of the untimed fill phase")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serving", type=int, default=24, help="requests in the serving sweep (0: skip)")
+    ap.add_argument("--kernel", action="store_true",
+                    help="time the history-integral kernel alone on a synthetic full-size history")
+    ap.add_argument("--kernel-slices", type=int, default=2500,
+                    help="history slices of --kernel (the solver's steady state holds about 2500)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the solver has no multi-GPU path; "
@@ -188,6 +268,9 @@ def main() -> int:
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.kernel:
+        print(json.dumps(kernel_bench(pk, args)), flush=True)
+        return 0
     prec = pk.FP64 if args.precision == "fp64" else pk.FP32_COMP
     params = workload_params(pk, prec)
     L = params.L
@@ -224,7 +307,8 @@ def main() -> int:
     value = steps / elapsed
     avg_ms = ms_hi / n_hi
     avg_slices = slices_hi / n_hi
-    achieved = hist_integral_bytes(L, avg_slices) / (avg_ms * 1e-3) / 1e9
+    alg_bytes = hist_integral_bytes(L, avg_slices, fp32=prec == pk.FP32_COMP)
+    achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
     out = {
         "metric": METRIC,
         "value": value,
@@ -263,13 +347,14 @@ def main() -> int:
             "peak": PEAK_HBM_GBS,
             "unit": "GB/s",
             "frac": achieved / PEAK_HBM_GBS,
-            "traffic": None,
+            "traffic": traffic_record(L, args.precision),
             "avg_launch_us": avg_ms * 1e3,
             "launches": n_hi,
-            "algorithmic_bytes_per_launch": hist_integral_bytes(L, avg_slices),
+            "algorithmic_bytes_per_launch": alg_bytes,
         },
     }
     s.close()
+    calibration_copies(torch)
     if args.serving > 0:
         out["serving"] = serving_sweep(pk, args.serving)
     if not args.no_cpu_baseline:

@@ -238,7 +238,21 @@ __device__ __forceinline__ int bracket_fast(const double* t, const int* bk, cons
     return bracket(t, lo, hi, s);
 }
 
-// One wavefront per row j (t' = theta_j t); lanes walk the quadrature nodes i.
+// Pair tiles.  A block owns kRowsPerBlock consecutive rows j (t' = theta_j t)
+// and has one wavefront per row.  Each wavefront iteration covers a tile of
+// kRowsPerWave rows x (64 / kRowsPerWave) consecutive nodes i; the block's
+// waves split the rows into groups of kRowsPerWave and the nodes into
+// kRowsPerWave interleaved phases, so one block iteration covers all its rows
+// x 64 nodes.  Tiles of several rows keep the 2-D stencil gathers of one
+// instruction within fewer cache lines (neighbouring rows read neighbouring
+// history points).
+constexpr int kRowsPerWave = 8;
+static_assert((kRowsPerWave == 1 || kRowsPerWave == 2 || kRowsPerWave == 4 || kRowsPerWave == 8) &&
+                  kRowsPerBlock % kRowsPerWave == 0, "rows per wave");
+constexpr int kColsPerWave = kWave / kRowsPerWave;
+constexpr int kPhases = kRowsPerWave;                 // waves sharing one row group
+constexpr int kGroups = kRowsPerBlock / kRowsPerWave;  // row groups of a block
+
 // Per pair (i, j) the kernel forms
 //   a = (C,R)(t, theta_i theta_j t)        index Lagrange on the stage slice
 //   b = (C,R)(t, phi t)                    phi = theta_j + (1-theta_j) theta_i
@@ -247,17 +261,20 @@ __device__ __forceinline__ int bracket_fast(const double* t, const int* bk, cons
 //                                          bracketing slices, then Hermite in t
 // (targets inside the current step use the quadratic through value and d/dt of
 // the last slice with a stored derivative and the stage slice), and the nine
-// nu-weighted row sums of the forward, transposed and dual equations; lane 0
-// assembles d/dt C(t, theta_j t) = d1C + theta_j d2C and likewise for R.
-// Body of the history-integral kernel for one block: rows
-// row_block * kRowsPerBlock ... of the instance described by `a`.
+// nu-weighted row sums of the forward, transposed and dual equations; one lane
+// per row assembles d/dt C(t, theta_j t) = d1C + theta_j d2C and likewise for R.
 // LDS of one block: t_n of the stored slices [nb], the bucket table [K+1]
-// ints (padded to 8 bytes) and, when YL, the stage slice [L].
+// ints (padded to 8 bytes), when YL the stage slice [L], and when the row
+// sums of a row are split over several waves, their partial sums.
 __host__ __device__ inline size_t lds_offset_y(int nb) {
     return (size_t(nb > 0 ? nb : 1) * 8 + (kBuckets + 2) * 4 + 15) / 16 * 16;
 }
-__host__ __device__ inline size_t lds_bytes(int nb, int L, bool yl) {
+__host__ __device__ inline size_t lds_offset_red(int nb, int L, bool yl) {
     return lds_offset_y(nb) + (yl ? size_t(L) * 16 : 0);
+}
+constexpr size_t kRedDoubles = kPhases > 1 ? size_t(kRowsPerBlock) * kPhases * 9 : 0;
+__host__ __device__ inline size_t lds_bytes(int nb, int L, bool yl) {
+    return lds_offset_red(nb, L, yl) + kRedDoubles * 8;
 }
 
 template <int S, int PM, class HP, bool YL>
@@ -295,15 +312,21 @@ __device__ __forceinline__ void hist_integral_block(const StageArgs& a, int row_
         __syncthreads();
     }
 
-    const int lane = threadIdx.x & (kWave - 1);
-    const int j = row_block * kRowsPerBlock + threadIdx.x / kWave;
-    if (j >= a.L) return;
     const int L = a.L;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    const int grp = wave % kGroups, ph = wave / kGroups;
+    const int r = lane / kColsPerWave, cl = lane % kColsPerWave;
+    const int row = grp * kRowsPerWave + r;  // row within the block
+    const int jr = row_block * kRowsPerBlock + row;
+    if (kPhases == 1 && jr >= L) return;     // whole wave past the end (no later barrier)
+    const bool valid = jr < L;
+    const int j = valid ? jr : L - 1;
     const HP* hist = static_cast<const HP*>(a.hist);
     const double t = a.t, thj = a.th[j], thcj = a.thc[j], tp = thj * t;
     const double tb = a.tb;
 
-    // row bracket for the c family (wave-uniform)
+    // row bracket for the c family
     int cmode;  // 0: stage slice only (t = 0), 1: slice 0, 2: Hermite, 3: in-step quadratic
     const HP* c0p = nullptr;
     const HP* c1p = nullptr;
@@ -344,21 +367,22 @@ __device__ __forceinline__ void hist_integral_block(const StageArgs& a, int row_
 
     double S1 = 0, S2 = 0, S3 = 0, S4 = 0, S5 = 0, S6 = 0, S7 = 0, S8 = 0, S9 = 0;
     double c0C = 0.0;
+    const int i0 = cl + kColsPerWave * ph;
 #pragma unroll 1
-    for (int i = lane; i < L; i += kWave) {
-        const double thi = a.th[i], w = a.nu[i];
+    for (int i = i0; i < L; i += kWave) {
+        const double thi = a.th[i], w = a.nu[i], xa = Xa[i], xb = Xb[L - 1 - i], xd = Xdj[i];
         double wl[S];
         // a: (t, theta_i theta_j)
         double aC, aR;
         {
-            const int base = lagrange<S>(Xa[i], L, wl);
+            const int base = lagrange<S>(xa, L, wl);
             interp2<S>(ysrc, base, wl, aC, aR);
         }
         // b: (t, phi)
         const double phi = fma(thcj, thi, thj);
         double bC, bR;
         {
-            const int base = lagrange<S>(double(L - 1) - Xb[L - 1 - i], L, wl);
+            const int base = lagrange<S>(double(L - 1) - xb, L, wl);
             interp2<S>(ysrc, base, wl, bC, bR);
         }
         // c: (t', theta_i)
@@ -386,7 +410,7 @@ __device__ __forceinline__ void hist_integral_block(const StageArgs& a, int row_
         double dC, dR;
         {
             HR wd[S];
-            const int base = lagrange<S, HR>(Xdj[i], L, wd);
+            const int base = lagrange<S, HR>(xd, L, wd);
             const double s = phi * t;
             if (nb == 0) {
                 double wy[S];
@@ -395,17 +419,16 @@ __device__ __forceinline__ void hist_integral_block(const StageArgs& a, int row_
                 interp2<S>(ysrc, base, wy, dC, dR);
             } else if (s <= tb) {
                 if (b == 0) {
-                    HR c, r;
-                    interp2h<S>(slot0, base, wd, c, r);
+                    HR c, r2;
+                    interp2h<S>(slot0, base, wd, c, r2);
                     dC = double(c);
-                    dR = double(r);
+                    dR = double(r2);
                 } else {
                     const int m = bracket_fast(s_t, s_bk, B, b, s);
                     const double h = s_t[m + 1] - s_t[m];
                     const double u = (s - s_t[m]) / h;
                     HR c0, r0, dc0, dr0, c1, r1, dc1, dr1;
                     interp4<S>(hist + size_t(a.slot[m]) * L, base, wd, c0, r0, dc0, dr0);
-                    __builtin_amdgcn_sched_barrier(0);  // bound the gathers in flight (registers)
                     interp4<S>(hist + size_t(a.slot[m + 1]) * L, base, wd, c1, r1, dc1, dr1);
                     const HR h00 = HR(2 * u * u * u - 3 * u * u + 1), h10 = HR((u * u * u - 2 * u * u + u) * h);
                     const HR h01 = HR(-2 * u * u * u + 3 * u * u), h11 = HR((u * u * u - u * u) * h);
@@ -440,25 +463,41 @@ __device__ __forceinline__ void hist_integral_block(const StageArgs& a, int row_
         S8 = fma(w, bR * f2d * dR, S8);
         S9 = fma(w, f2c * cR * cC + f1c * cR, S9);
     }
-    S1 = wave_sum(S1);
-    S2 = wave_sum(S2);
-    S3 = wave_sum(S3);
-    S4 = wave_sum(S4);
-    S5 = wave_sum(S5);
-    S6 = wave_sum(S6);
-    S7 = wave_sum(S7);
-    S8 = wave_sum(S8);
-    S9 = wave_sum(S9);
-    if (lane == 0) {
+    double Sv[9] = {S1, S2, S3, S4, S5, S6, S7, S8, S9};
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {  // sum over the lanes of the row (fixed order)
+#pragma unroll
+        for (int off = kColsPerWave / 2; off > 0; off >>= 1) Sv[k] += __shfl_xor(Sv[k], off, kWave);
+    }
+    bool assemble = cl == 0;
+    if (kPhases > 1) {  // rows split over waves: partial sums through LDS, summed in phase order
+        double* red = reinterpret_cast<double*>(reinterpret_cast<char*>(smem) + lds_offset_red(nb, L, YL));
+        __syncthreads();  // every wave is done with the stage slice region and the bracket tables
+        if (cl == 0) {
+#pragma unroll
+            for (int k = 0; k < 9; ++k) red[(row * kPhases + ph) * 9 + k] = Sv[k];
+        }
+        __syncthreads();
+        assemble = cl == 0 && ph == 0;
+        if (assemble) {
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                double v = red[(row * kPhases) * 9 + k];
+                for (int q = 1; q < kPhases; ++q) v += red[(row * kPhases + q) * 9 + k];
+                Sv[k] = v;
+            }
+        }
+    }
+    if (assemble && valid) {
         const double mu = a.mue[0];
         const YPoint y0 = a.y[0], yj = a.y[j];
         const double T = a.m.T, be = a.m.beta0;
-        const double d1C = -mu * yj.c + t * (thj * S1 + thj * S2 + thcj * S3) + be * fD1<PM>(a.m, y0.c) * c0C;
-        const double d1R = -mu * yj.r + t * thcj * S4;
-        const double mup = T + t * thj * S9 + be * fD1<PM>(a.m, c0C) * c0C;
-        const double d2C = -mup * yj.c + t * (thj * S5 + thj * S6 + thcj * S7) + 2.0 * T * yj.r +
+        const double d1C = -mu * yj.c + t * (thj * Sv[0] + thj * Sv[1] + thcj * Sv[2]) + be * fD1<PM>(a.m, y0.c) * c0C;
+        const double d1R = -mu * yj.r + t * thcj * Sv[3];
+        const double mup = T + t * thj * Sv[8] + be * fD1<PM>(a.m, c0C) * c0C;
+        const double d2C = -mup * yj.c + t * (thj * Sv[4] + thj * Sv[5] + thcj * Sv[6]) + 2.0 * T * yj.r +
                            be * fD1<PM>(a.m, c0C) * y0.c;
-        const double d2R = mup * yj.r - t * thcj * S8;
+        const double d2R = mup * yj.r - t * thcj * Sv[7];
         double oc = d1C + thj * d2C, orr = d1R + thj * d2R;
         if (j == L - 1) {
             a.diag[0] = oc;
@@ -596,6 +635,25 @@ __device__ __forceinline__ HPoint up(const HPoint32& v) {
 __device__ __forceinline__ double herm_int(double h, double ya, double da, double yb, double db) {
     return h * (ya + yb) * 0.5 + h * h * (da - db) * (1.0 / 12.0);
 }
+// Rounding allowance of an FP32 history: a stored value differs from the FP64
+// value it was rounded from by at most u |stored| (u = 2^-24), so the residual
+// of the stored values differs from the residual of the FP64 values by at most
+// the sum over points of u times |coefficient| |stored| over the six values of
+// each field.  The coefficients of the residual in the values at n-1, n, n+1
+// are -h2/2, h3/2, -h1/2 and in the derivatives (h1^2-h3^2)/12,
+// (h2^2-h1^2)/12, (h3^2-h2^2)/12.
+template <class HP> struct RoundingAllowance {
+    static constexpr bool on = false;
+};
+template <> struct RoundingAllowance<HPoint32> {
+    static constexpr bool on = true;
+};
+constexpr double kUnitRoundoff32 = 5.9604644775390625e-8;  // 2^-24
+
+// eps_n = sum_i |Delta^C_i| + |Delta^R_i| for candidate n (Sec. 3.6), with
+// Delta = H[n-1,n] + H[n,n+1] - H[n-1,n+1].  For an FP32 history the rounding
+// allowance is subtracted (never below zero), so a slice is kept only if its
+// residual exceeds what the storage precision can resolve by eps/10.
 template <class HP>
 __global__ __launch_bounds__(256) void k_sparsify_residual(int L, int first, const double* __restrict__ thist,
                                                            const int* __restrict__ slot, const HP* __restrict__ hist,
@@ -606,7 +664,10 @@ __global__ __launch_bounds__(256) void k_sparsify_residual(int L, int first, con
     const HP* pc = hist + size_t(slot[n]) * L;
     const HP* pb = hist + size_t(slot[n + 1]) * L;
     const double h1 = thist[n] - thist[n - 1], h2 = thist[n + 1] - thist[n], h3 = thist[n + 1] - thist[n - 1];
-    double e = 0.0;
+    const double ka = 0.5 * h2, kc = 0.5 * h3, kb = 0.5 * h1;
+    const double qa = fabs(h1 * h1 - h3 * h3) * (1.0 / 12.0), qc = fabs(h2 * h2 - h1 * h1) * (1.0 / 12.0),
+                 qb = fabs(h3 * h3 - h2 * h2) * (1.0 / 12.0);
+    double e = 0.0, bound = 0.0;
     for (int i = threadIdx.x; i < L; i += blockDim.x) {
         const HPoint va = up(pa[i]), vc = up(pc[i]), vb = up(pb[i]);
         const double dc = herm_int(h1, va.c, va.dc, vc.c, vc.dc) + herm_int(h2, vc.c, vc.dc, vb.c, vb.dc) -
@@ -614,8 +675,16 @@ __global__ __launch_bounds__(256) void k_sparsify_residual(int L, int first, con
         const double dr = herm_int(h1, va.r, va.dr, vc.r, vc.dr) + herm_int(h2, vc.r, vc.dr, vb.r, vb.dr) -
                           herm_int(h3, va.r, va.dr, vb.r, vb.dr);
         e += fabs(dc) + fabs(dr);
+        if (RoundingAllowance<HP>::on)
+            bound += ka * (fabs(va.c) + fabs(va.r)) + kc * (fabs(vc.c) + fabs(vc.r)) + kb * (fabs(vb.c) + fabs(vb.r)) +
+                     qa * (fabs(va.dc) + fabs(va.dr)) + qc * (fabs(vc.dc) + fabs(vc.dr)) +
+                     qb * (fabs(vb.dc) + fabs(vb.dr));
     }
     e = block_sum(e, sh);
+    if (RoundingAllowance<HP>::on) {
+        bound = block_sum(bound, sh) * kUnitRoundoff32;
+        e = e > bound ? e - bound : 0.0;
+    }
     if (threadIdx.x == 0) eps_n[n] = e;
 }
 

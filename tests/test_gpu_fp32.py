@@ -78,3 +78,31 @@ def test_fp32_run_against_fp64_run():
     eC = np.max(np.abs(CubicSpline(t32[t32 > 2.5], cw32)(tq2) - CubicSpline(t64[t64 > 2.5], cw64)(tq2)))
     say(f"  |dE| {eE:.2e}  |dmu| {emu:.2e}  |dC(t, 2)| {eC:.2e}")
     assert eE <= 1e-6 and emu <= 1e-5 and eC <= 1e-5
+
+
+def test_fp32_run_with_sparsification_against_fp64_run():
+    """A low-temperature solve whose history must be sparsified to fit (cap 512
+    slices): the FP32-comp residual, less its rounding allowance, still lets
+    sparsification free slices, the solve reaches t_max, and its energy stays
+    within 1e-6 of the FP64 solve's."""
+    say("fp32 run with sparsification vs fp64 run")
+    terms, T, L = {2: 0.499, 3: 0.184, 4: 0.317}, 0.477, 512
+    runs = {}
+    for prec in (pk.FP64, pk.FP32_COMP):
+        s = pk.Solver(pk.make_params(terms, T, t_max=36.0, L=L, M_cap=512, eps=1e-6, dt0=1e-3, dt_min=1e-12,
+                                     precision=prec))
+        st, info = s.step(float("inf"))
+        assert st == pk.DONE
+        runs[prec] = (s.read(pk.F_T_GRID), s.read(pk.F_ENERGY), s.read(pk.F_MU), info)
+        say(f"  precision={prec}: steps={info.accepted} rejected={info.rejected} M={info.M} "
+            f"removed={info.removed} t={info.t:.4g}")
+        s.close()
+    from scipy.interpolate import CubicSpline
+    t64, E64, mu64, i64 = runs[pk.FP64]
+    t32, E32, mu32, i32 = runs[pk.FP32_COMP]
+    assert i32.removed > 0
+    tq = np.linspace(1.0, 35.0, 69)
+    eE = np.max(np.abs(CubicSpline(t32, E32)(tq) - CubicSpline(t64, E64)(tq)))
+    emu = np.max(np.abs(CubicSpline(t32, mu32)(tq) - CubicSpline(t64, mu64)(tq)))
+    say(f"  |dE| {eE:.2e}  |dmu| {emu:.2e}")
+    assert eE <= 1e-6 and emu <= 1e-5

@@ -10,7 +10,10 @@ Phases: (1) untimed fill from t = 0 until the history first reaches its
 capacity and an automatic sparsification pass has run (the steady state of
 the method), (2) W untimed warm-up steps, (3) exactly K timed steps between
 device synchronisations.  Per-kernel durations are HIP events recorded by the
-library on its own stream during (3).
+library on its own stream during (3).  The line's value is the --precision
+solve (FP64 by default); the same three phases then run for the other
+precision (FP32-compensated history by default) and are reported beside it.
+Then come the serving sweep and the CPU baseline (the oracle).
 
 One JSON line is printed on stdout; progress goes to stderr.
 """
@@ -251,6 +254,7 @@ def main() -> int:
     ap.add_argument("--precision", choices=["fp64", "fp32c"], default="fp64")
     ap.add_argument("--fill-seconds", type=float, default=150.0, help="time budget of the untimed fill phase")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true", help="skip the timed window at the other precision")
     ap.add_argument("--serving", type=int, default=24, help="requests in the serving sweep (0: skip)")
     ap.add_argument("--kernel", action="store_true",
                     help="time the history-integral kernel alone on a synthetic full-size history")
@@ -271,7 +275,48 @@ def main() -> int:
     if args.kernel:
         print(json.dumps(kernel_bench(pk, args)), flush=True)
         return 0
-    prec = pk.FP64 if args.precision == "fp64" else pk.FP32_COMP
+    prec_name = args.precision
+    other = "fp32c" if prec_name == "fp64" else "fp64"
+    w = timed_window(pk, torch, prec_name, args)
+    L = w["L"]
+    out = {
+        "metric": METRIC,
+        "value": w["steps_per_s"],
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": w["steps"],
+        "warmup": args.warmup,
+        "ms_per_step": w["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec_name == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": w["config"],
+        "roofline": w["roofline"],
+    }
+    calibration_copies(torch)
+    if not args.no_compare:
+        o = timed_window(pk, torch, other, args)
+        out[other] = {"value": o["steps_per_s"], "unit": "steps/s", "ms_per_step": o["ms_per_step"],
+                      "speedup_vs_" + prec_name: o["steps_per_s"] / w["steps_per_s"],
+                      "M_window": o["config"]["M_window"], "t_window": o["config"]["t_window"],
+                      "rhs_evals_per_step": o["config"]["rhs_evals_per_step"],
+                      "hist_integral_avg_launch_us": o["roofline"]["avg_launch_us"],
+                      "roofline": o["roofline"]}
+    if args.serving > 0:
+        out["serving"] = serving_sweep(pk, args.serving)
+    if not args.no_cpu_baseline:
+        sl = w["config"]["mean_slices_per_stage"]
+        out["cpu_baseline"] = cpu_baseline(L, int(round(sl)) if sl > 16 else L,
+                                           w["config"]["rhs_evals_per_step"])
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def timed_window(pk, torch, prec_name: str, args) -> dict:
+    """Fill, warm up and time one solve of the workload at the given precision."""
+    prec = pk.FP64 if prec_name == "fp64" else pk.FP32_COMP
     params = workload_params(pk, prec)
     L = params.L
     s = pk.Solver(params)
@@ -281,8 +326,9 @@ def main() -> int:
     steady = False
     while time.perf_counter() - t_fill < args.fill_seconds:
         _, info = s.step(float("inf"), 250)
-        log(f"fill: steps={info.accepted + info.rejected} M={info.M} t={info.t:.5g} dt={info.dt:.3g} "
-            f"scheme={info.scheme} sparsify={info.sparsify_calls} ({time.perf_counter() - t_fill:.1f} s)")
+        log(f"fill ({prec_name}): steps={info.accepted + info.rejected} M={info.M} t={info.t:.5g} "
+            f"dt={info.dt:.3g} scheme={info.scheme} sparsify={info.sparsify_calls} "
+            f"({time.perf_counter() - t_fill:.1f} s)")
         if info.sparsify_calls >= 1:
             steady = True
             break
@@ -301,31 +347,24 @@ def main() -> int:
     n_pr, ms_pr, _ = s.timing_read(pk.K_STAGE_PREP)
     n_rk, ms_rk, _ = s.timing_read(pk.K_RK)
     s.timing(False)
+    s.close()
     steps = (i1.accepted + i1.rejected) - (i0.accepted + i0.rejected)
     assert steps == args.steps, (steps, args.steps)
     evals = i1.rhs_evals - i0.rhs_evals
-    value = steps / elapsed
     avg_ms = ms_hi / n_hi
     avg_slices = slices_hi / n_hi
     alg_bytes = hist_integral_bytes(L, avg_slices, fp32=prec == pk.FP32_COMP)
     achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
-    out = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "steps/s",
-        "n_gpus": 1,
+    log(f"window ({prec_name}): {steps} steps in {elapsed:.3f} s, hist_integral {avg_ms * 1e3:.1f} us/launch")
+    return {
+        "L": L,
         "steps": steps,
-        "warmup": args.warmup,
+        "steps_per_s": steps / elapsed,
         "ms_per_step": 1e3 * elapsed / steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64" if prec == pk.FP64 else "f32+f64",
-        "data": "synthetic",
         "config": {
             "workload": "mixed spherical 3+4 (a3^2=a4^2=1/2), T=0.55, t_max=1e7, theta grid L=4096, "
                         "history cap 4096, eps=1e-8, DP5 then SSPRK(10,4), automatic sparsification",
-            "precision": args.precision,
+            "precision": prec_name,
             "L": L,
             "M_cap": params.M_cap,
             "steady_state": steady,
@@ -347,20 +386,12 @@ def main() -> int:
             "peak": PEAK_HBM_GBS,
             "unit": "GB/s",
             "frac": achieved / PEAK_HBM_GBS,
-            "traffic": traffic_record(L, args.precision),
+            "traffic": traffic_record(L, prec_name),
             "avg_launch_us": avg_ms * 1e3,
             "launches": n_hi,
             "algorithmic_bytes_per_launch": alg_bytes,
         },
     }
-    s.close()
-    calibration_copies(torch)
-    if args.serving > 0:
-        out["serving"] = serving_sweep(pk, args.serving)
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(L, int(round(avg_slices)) if avg_slices > 16 else L, evals / steps)
-    print(json.dumps(out), flush=True)
-    return 0
 
 
 if __name__ == "__main__":

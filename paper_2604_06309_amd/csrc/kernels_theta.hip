@@ -279,7 +279,13 @@ __host__ __device__ inline size_t lds_bytes(int nb, int L, bool yl) {
 
 template <int S, int PM, class HP, bool YL>
 __device__ __forceinline__ void hist_integral_block(const StageArgs& a, int row_block) {
-    using HR = hreal_t<HP>;  // arithmetic on values read from the history
+    // All arithmetic is FP64, also on an FP32 history: values are widened as
+    // they are loaded.  (FP32 arithmetic is no faster than FP64 on this chip
+    // without packed instructions, and its rounding, unlike the rounding of the
+    // stored values, differs from stage to stage and would reach the embedded
+    // error estimate.)
+    using HR = double;
+    using HS = hreal_t<HP>;  // storage type of the history
     extern __shared__ double smem[];
     const int nb = a.nb;
     const int b = nb - 1;
@@ -429,6 +435,9 @@ __device__ __forceinline__ void hist_integral_block(const StageArgs& a, int row_
                     const double u = (s - s_t[m]) / h;
                     HR c0, r0, dc0, dr0, c1, r1, dc1, dr1;
                     interp4<S>(hist + size_t(a.slot[m]) * L, base, wd, c0, r0, dc0, dr0);
+                    // FP32 storage: values are widened as they arrive, so the second slice's
+                    // gathers wait for the first (keeps the widened values within registers)
+                    if constexpr (sizeof(HS) == 4) __builtin_amdgcn_sched_barrier(0);
                     interp4<S>(hist + size_t(a.slot[m + 1]) * L, base, wd, c1, r1, dc1, dr1);
                     const HR h00 = HR(2 * u * u * u - 3 * u * u + 1), h10 = HR((u * u * u - 2 * u * u + u) * h);
                     const HR h01 = HR(-2 * u * u * u + 3 * u * u), h11 = HR((u * u * u - u * u) * h);
@@ -508,8 +517,8 @@ __device__ __forceinline__ void hist_integral_block(const StageArgs& a, int row_
         a.kout[j] = YPoint{oc, orr};
         if (a.store) {
             HP* st = static_cast<HP*>(a.store);
-            st[j].dc = HR(oc);
-            st[j].dr = HR(orr);
+            st[j].dc = HS(oc);
+            st[j].dr = HS(orr);
         }
     }
 }

@@ -1,12 +1,12 @@
-"""The FP32-compensated form (history stored in FP32, stencil arithmetic on it in
-FP32, row sums accumulated in FP64; mu, RK, control and sparsification in FP64)
-against the FP64 oracle and the FP64 solver.
+"""The FP32-compensated form (history stored in FP32 and widened to FP64 as it
+is read; every sum, mu, RK, control and sparsification in FP64) against the
+FP64 oracle and the FP64 solver.
 
 Bars: one right-hand-side evaluation within 2e-6 of the term scale
 (|mu| + T + max|out|): the stored values carry FP32 rounding (6e-8 relative)
-and the 2-D stencil adds a few such roundings.  Runs: the energy and mu of
-the FP32-comp solver stay within 1e-6 of the FP64 solver's at every common
-stored time of a short run.
+and the quadrature sums of up to 4096 such values keep it below 1e-6.  Runs:
+energy and mu of the FP32-comp solver against the FP64 solver's at common
+times (splines through each run's stored times), per test below.
 """
 import sys
 
@@ -106,3 +106,29 @@ def test_fp32_run_with_sparsification_against_fp64_run():
     emu = np.max(np.abs(CubicSpline(t32, mu32)(tq) - CubicSpline(t64, mu64)(tq)))
     say(f"  |dE| {eE:.2e}  |dmu| {emu:.2e}")
     assert eE <= 1e-6 and emu <= 1e-5
+
+
+def test_fp32_controller_not_limited_by_rounding():
+    """At the workload's tolerance (1e-8) and a grid of 1024 points, the embedded
+    error estimate of the FP32-comp solver must see the solution's error, not
+    rounding: it takes the same number of steps as the FP64 solver to t = 30
+    (within 2%), with the energy within 1e-7 of the FP64 solve's."""
+    say("fp32 controller at eps=1e-8")
+    terms, T, L = {3: 0.5, 4: 0.5}, 0.55, 1024
+    runs = {}
+    for prec in (pk.FP64, pk.FP32_COMP):
+        s = pk.Solver(pk.make_params(terms, T, t_max=1e7, L=L, M_cap=4096, eps=1e-8, dt0=1e-3, dt_min=1e-12,
+                                     precision=prec))
+        st, info = s.step(30.0)
+        runs[prec] = (s.read(pk.F_T_GRID), s.read(pk.F_ENERGY), info)
+        say(f"  precision={prec}: steps={info.accepted} rejected={info.rejected} t={info.t:.4g} dt={info.dt:.3g}")
+        s.close()
+    from scipy.interpolate import CubicSpline
+    t64, E64, i64 = runs[pk.FP64]
+    t32, E32, i32 = runs[pk.FP32_COMP]
+    assert abs(i32.accepted - i64.accepted) <= 0.02 * i64.accepted
+    assert i32.rejected <= i64.rejected + 2
+    tq = np.linspace(1.0, 29.0, 57)
+    eE = np.max(np.abs(CubicSpline(t32, E32)(tq) - CubicSpline(t64, E64)(tq)))
+    say(f"  |dE| {eE:.2e}")
+    assert eE <= 1e-7

@@ -67,7 +67,12 @@ enum { DMFE_MAX_TERMS = 8, DMFE_MAX_P = 16 };
  *   T, beta0            bath temperature, inverse temperature of the initial state
  *   t_max               largest simulated time; sets gamma = -W_{-1}(-1/t_max) (needs t_max > e)
  *   mode                DMFE_UNIFORM or DMFE_ADAPTIVE
- *   precision           DMFE_FP64 (only value accepted by DMFE_UNIFORM) or DMFE_FP32_COMP
+ *   precision           DMFE_FP64 (only value accepted by DMFE_UNIFORM) or DMFE_FP32_COMP:
+ *                       the history (C, R and their t-derivatives) is stored in FP32 and
+ *                       widened to FP64 as it is read; all arithmetic, mu, the RK error,
+ *                       the controller and the sparsification decision stay FP64.  The
+ *                       sparsification residual of an FP32 history has a bound on the
+ *                       FP32 rounding of the stored values subtracted (never below 0).
  * uniform mode:
  *   h, N                step and number of steps (t_max is ignored)
  * adaptive mode:

@@ -125,7 +125,8 @@ Layout make_layout(const dmfe_params& p) {
     };
     if (p.mode == DMFE_ADAPTIVE) {
         const size_t L = size_t(p.L), Mc = size_t(p.M_cap > 0 ? p.M_cap : p.L);
-        lo.hist = take(Mc * L * (p.precision == DMFE_FP32_COMP ? sizeof(HPoint32) : sizeof(HPoint)));
+        // Mc history slots and the stage slot after them
+        lo.hist = take((Mc + 1) * L * (p.precision == DMFE_FP32_COMP ? sizeof(HPoint32) : sizeof(HPoint)));
         lo.thist = take(Mc * sizeof(double));
         lo.slot = take(Mc * sizeof(int));
         lo.th = take(L * sizeof(double));
@@ -266,6 +267,7 @@ StageArgs stage_args(const dmfe_handle* h, double t, int nb, const YPoint* y, YP
     a.thist = h->at<double>(h->lo.thist);
     a.slot = h->at<int>(h->lo.slot);
     a.hist = h->at<void>(h->lo.hist);
+    a.stage = stage_slot(h);
     a.fp32 = h->fp32;
     a.y = y;
     a.mue = h->at<double>(h->lo.mue);
@@ -279,7 +281,8 @@ StageArgs stage_args(const dmfe_handle* h, double t, int nb, const YPoint* y, YP
 // one right-hand-side evaluation: mu(t) then the history integrals
 dmfe_status eval_rhs(dmfe_handle* h, double t, int nb, const YPoint* y, YPoint* kout, void* store) {
     auto* e1 = timing_begin(h, DMFE_K_STAGE_PREP, 0);
-    HCHK(launch_stage_prep(h->m, h->L, t, h->at<double>(h->lo.nu), y, h->at<double>(h->lo.mue), h->stream));
+    HCHK(launch_stage_prep(h->m, h->L, t, h->at<double>(h->lo.nu), y, h->at<double>(h->lo.mue), stage_slot(h),
+                           h->fp32, h->stream));
     timing_end(h, e1);
     auto* e2 = timing_begin(h, DMFE_K_HIST_INTEGRAL, nb);
     HCHK(launch_hist_integral(stage_args(h, t, nb, y, kout, store), h->s, h->stream));
@@ -291,6 +294,9 @@ dmfe_status eval_rhs(dmfe_handle* h, double t, int nb, const YPoint* y, YPoint* 
 size_t point_bytes(const dmfe_handle* h) { return h->fp32 ? sizeof(HPoint32) : sizeof(HPoint); }
 void* slot_ptr(dmfe_handle* h, int slot) {
     return h->at<char>(h->lo.hist) + size_t(slot) * h->L * point_bytes(h);
+}
+void* stage_slot(const dmfe_handle* h) {
+    return const_cast<dmfe_handle*>(h)->at<char>(h->lo.hist) + size_t(h->Mc) * h->L * point_bytes(h);
 }
 
 dmfe_status upload_order(dmfe_handle* h) {

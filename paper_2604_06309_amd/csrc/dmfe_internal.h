@@ -55,6 +55,7 @@ struct StageArgs {
     const double* thist; // t_n in logical order [>= nb]
     const int* slot;     // slot of logical slice n [>= nb]
     const void* hist;    // history slots [M_cap][L] of HPoint (fp64) or HPoint32 (fp32 histories)
+    const void* stage;   // the stage slice in history format [L] (written by the stage prep)
     const YPoint* y;     // stage slice [L]
     const double* mue;   // mu(t), E(t) of the stage slice [2]
     YPoint* kout;        // d/dt C, d/dt R along fixed theta [L]
@@ -79,7 +80,7 @@ struct GridArgs {
 // launchers (kernels_theta.hip); all return hipError_t of the launch
 hipError_t launch_coords(const GridArgs& g, hipStream_t st);
 hipError_t launch_stage_prep(const Model& m, int L, double t, const double* nu, const YPoint* y, double* mue,
-                             hipStream_t st);
+                             void* stage, int fp32, hipStream_t st);
 hipError_t launch_hist_integral(const StageArgs& a, int s, hipStream_t st);
 hipError_t launch_rk_combine(int L, const YPoint* y0, const YPoint* k, int nk, const double* coef, double dt,
                              YPoint* ys, hipStream_t st);
@@ -114,7 +115,9 @@ struct PrepDesc {
     const YPoint* y;
     const double* nu;
     double* mue;
+    void* stage;  // the stage slice in history format [L]
     int L;
+    int fp32;
     double t;
     Model m;
 };

@@ -111,6 +111,7 @@ void timing_end(dmfe_handle* h, dmfe_handle::EvPair* p);
 void timing_drain(dmfe_handle* h);
 
 StageArgs stage_args(const dmfe_handle* h, double t, int nb, const YPoint* y, YPoint* kout, void* store);
+void* stage_slot(const dmfe_handle* h);  // the stage slice in history format, after the Mc slots
 dmfe_status eval_rhs(dmfe_handle* h, double t, int nb, const YPoint* y, YPoint* kout, void* store);
 size_t point_bytes(const dmfe_handle* h);
 void* slot_ptr(dmfe_handle* h, int slot);

@@ -129,11 +129,11 @@ template <> struct HReal<HPoint> { using type = double; };
 template <> struct HReal<HPoint32> { using type = float; };
 template <class HP> using hreal_t = typename HReal<HP>::type;
 
-template <int S>
+template <int S, int U = S>
 __device__ __forceinline__ void interp2(const YPoint* row, int base, const double (&w)[S], double& c, double& r) {
     c = 0.0;
     r = 0.0;
-#pragma unroll
+#pragma unroll U
     for (int k = 0; k < S; ++k) {
         const YPoint v = row[base + k];
         c = fma(w[k], v.c, c);
@@ -152,17 +152,6 @@ __device__ __forceinline__ void interp4(const HP* row, int base, const R (&w)[S]
         dr = fma(w[k], v.dr, dr);
     }
 }
-template <int S, class HP, class R = hreal_t<HP>>
-__device__ __forceinline__ void interp2h(const HP* row, int base, const R (&w)[S], R& c, R& r) {
-    c = R(0);
-    r = R(0);
-#pragma unroll
-    for (int k = 0; k < S; ++k) {
-        const HP v = row[base + k];
-        c = fma(w[k], v.c, c);
-        r = fma(w[k], v.r, r);
-    }
-}
 
 // largest m in [lo, hi-1] with t[m] <= x, given t[lo] <= x <= t[hi]
 __device__ __forceinline__ int bracket(const double* t, int lo, int hi, double x) {
@@ -177,13 +166,29 @@ __device__ __forceinline__ int bracket(const double* t, int lo, int hi, double x
 // ---------------------------------------------------------------- stage prep: mu(t), E(t)
 // mu(t) = T + t sum_i nu_i [f''(C)RC + f'(C)R]_i + beta0 f'(C_0) C_0 and
 // E(t) = -t sum_i nu_i f'(C_i) R_i - beta0 f(C_0) on the stage slice (Sec. 2.1).
+// The same pass writes the stage slice into the stage slot in history format,
+// so that targets inside the current step are gathered like stored ones: an
+// FP64 slot holds (C, R, 0, 0); an FP32 slot holds the FP32 value and its
+// rounding remainder (C_hi, R_hi, C - C_hi, R - R_hi), which a reader weighting
+// both fields equally sums back to the FP64 value up to 2^-48.
+__device__ __forceinline__ void write_stage_point(void* stage, int fp32, int i, const YPoint& v) {
+    if (fp32) {
+        const float ch = float(v.c), rh = float(v.r);
+        static_cast<HPoint32*>(stage)[i] = HPoint32{ch, rh, float(v.c - double(ch)), float(v.r - double(rh))};
+    } else {
+        static_cast<HPoint*>(stage)[i] = HPoint{v.c, v.r, 0.0, 0.0};
+    }
+}
+
 template <int PM>
 __device__ __forceinline__ void stage_prep_body(const Model& m, int L, double t, const double* __restrict__ nu,
-                                                const YPoint* __restrict__ y, double* __restrict__ mue) {
+                                                const YPoint* __restrict__ y, double* __restrict__ mue, void* stage,
+                                                int fp32) {
     __shared__ double sh[16];
     double sk = 0.0, se = 0.0;
     for (int i = threadIdx.x; i < L; i += blockDim.x) {
         const YPoint v = y[i];
+        write_stage_point(stage, fp32, i, v);
         const double d1 = fD1<PM>(m, v.c), d2 = fD2<PM>(m, v.c);
         sk = fma(nu[i], d2 * v.r * v.c + d1 * v.r, sk);
         se = fma(nu[i], d1 * v.r, se);
@@ -198,13 +203,14 @@ __device__ __forceinline__ void stage_prep_body(const Model& m, int L, double t,
 }
 template <int PM>
 __global__ __launch_bounds__(1024) void k_stage_prep(const Model m, int L, double t, const double* __restrict__ nu,
-                                                     const YPoint* __restrict__ y, double* __restrict__ mue) {
-    stage_prep_body<PM>(m, L, t, nu, y, mue);
+                                                     const YPoint* __restrict__ y, double* __restrict__ mue,
+                                                     void* stage, int fp32) {
+    stage_prep_body<PM>(m, L, t, nu, y, mue, stage, fp32);
 }
 template <int PM>
 __global__ __launch_bounds__(1024) void k_stage_prep_multi(const PrepDesc* __restrict__ d) {
     const PrepDesc& q = d[blockIdx.x];
-    stage_prep_body<PM>(q.m, q.L, q.t, q.nu, q.y, q.mue);
+    stage_prep_body<PM>(q.m, q.L, q.t, q.nu, q.y, q.mue, q.stage, q.fp32);
 }
 
 // ---------------------------------------------------------------- the history integrals
@@ -238,20 +244,33 @@ __device__ __forceinline__ int bracket_fast(const double* t, const int* bk, cons
     return bracket(t, lo, hi, s);
 }
 
-// Pair tiles.  A block owns kRowsPerBlock consecutive rows j (t' = theta_j t)
-// and has one wavefront per row.  Each wavefront iteration covers a tile of
-// kRowsPerWave rows x (64 / kRowsPerWave) consecutive nodes i; the block's
-// waves split the rows into groups of kRowsPerWave and the nodes into
-// kRowsPerWave interleaved phases, so one block iteration covers all its rows
-// x 64 nodes.  Tiles of several rows keep the 2-D stencil gathers of one
-// instruction within fewer cache lines (neighbouring rows read neighbouring
-// history points).
+// Pair tiles.  A block owns kRowsPerBlock consecutive rows j (t' = theta_j t).
+// Each wavefront iteration covers a tile of kRowsPerWave rows x (64 /
+// kRowsPerWave) consecutive nodes i; the block's waves split its rows into
+// groups of kRowsPerWave and the nodes into `phases` interleaved sets, so one
+// block iteration covers all its rows x (8 x phases) nodes.  Tiles of several
+// rows keep the 2-D stencil gathers of one instruction within fewer cache lines
+// (neighbouring rows read neighbouring history points).
 constexpr int kRowsPerWave = 8;
-static_assert((kRowsPerWave == 1 || kRowsPerWave == 2 || kRowsPerWave == 4 || kRowsPerWave == 8) &&
-                  kRowsPerBlock % kRowsPerWave == 0, "rows per wave");
+static_assert(kRowsPerBlock % kRowsPerWave == 0, "rows per wave");
 constexpr int kColsPerWave = kWave / kRowsPerWave;
-constexpr int kPhases = kRowsPerWave;                 // waves sharing one row group
 constexpr int kGroups = kRowsPerBlock / kRowsPerWave;  // row groups of a block
+
+// Tile configuration per history storage type, chosen by measurement at the
+// L = 4096 workload.  FP64: 12 waves per block (3 per SIMD, 125 VGPRs) with the
+// 2-D stencil issued first in the iteration, so its gathers overlap the
+// stage-slice stencils; FP32: 8 waves per block with the stage-slice stencils
+// first.
+template <class HP> struct HistCfg;
+template <> struct HistCfg<HPoint> {
+    static constexpr int phases = 12;
+    static constexpr bool d_first = true;
+};
+template <> struct HistCfg<HPoint32> {
+    static constexpr int phases = 8;
+    static constexpr bool d_first = false;
+};
+template <class HP> constexpr int hist_threads() { return kGroups * HistCfg<HP>::phases * kWave; }
 
 // Per pair (i, j) the kernel forms
 //   a = (C,R)(t, theta_i theta_j t)        index Lagrange on the stage slice
@@ -272,9 +291,10 @@ __host__ __device__ inline size_t lds_offset_y(int nb) {
 __host__ __device__ inline size_t lds_offset_red(int nb, int L, bool yl) {
     return lds_offset_y(nb) + (yl ? size_t(L) * 16 : 0);
 }
-constexpr size_t kRedDoubles = kPhases > 1 ? size_t(kRowsPerBlock) * kPhases * 9 : 0;
+template <class HP>
 __host__ __device__ inline size_t lds_bytes(int nb, int L, bool yl) {
-    return lds_offset_red(nb, L, yl) + kRedDoubles * 8;
+    constexpr int ph = HistCfg<HP>::phases;
+    return lds_offset_red(nb, L, yl) + (ph > 1 ? size_t(kRowsPerBlock) * ph * 9 * 8 : 0);
 }
 
 template <int S, int PM, class HP, bool YL>
@@ -284,8 +304,9 @@ __device__ __forceinline__ void hist_integral_block(const StageArgs& a, int row_
     // without packed instructions, and its rounding, unlike the rounding of the
     // stored values, differs from stage to stage and would reach the embedded
     // error estimate.)
-    using HR = double;
     using HS = hreal_t<HP>;  // storage type of the history
+    constexpr int kPhases = HistCfg<HP>::phases;
+    constexpr int kColStride = kColsPerWave * kPhases;  // nodes one block iteration covers
     extern __shared__ double smem[];
     const int nb = a.nb;
     const int b = nb - 1;
@@ -332,41 +353,45 @@ __device__ __forceinline__ void hist_integral_block(const StageArgs& a, int row_
     const double t = a.t, thj = a.th[j], thcj = a.thc[j], tp = thj * t;
     const double tb = a.tb;
 
-    // row bracket for the c family
-    int cmode;  // 0: stage slice only (t = 0), 1: slice 0, 2: Hermite, 3: in-step quadratic
-    const HP* c0p = nullptr;
-    const HP* c1p = nullptr;
-    HR cw0 = 0, cw1 = 0, cw2 = 0, cw3 = 0;
-    if (nb == 0) {
-        cmode = 0;
-    } else if (tp <= tb) {
-        if (b == 0) {
-            cmode = 1;
-            c0p = hist + size_t(a.slot[0]) * L;
-        } else {
-            cmode = 2;
-            const int m = bracket(s_t, 0, b, tp);
-            const double h = s_t[m + 1] - s_t[m];
-            const double u = (tp - s_t[m]) / h;
-            cw0 = HR(2 * u * u * u - 3 * u * u + 1);
-            cw1 = HR((u * u * u - 2 * u * u + u) * h);
-            cw2 = HR(-2 * u * u * u + 3 * u * u);
-            cw3 = HR((u * u * u - u * u) * h);
-            c0p = hist + size_t(a.slot[m]) * L;
-            c1p = hist + size_t(a.slot[m + 1]) * L;
-        }
-    } else {
-        cmode = 3;
-        const double h = t - tb;
-        const double u = (tp - tb) / h;
-        cw0 = HR(1.0 - u * u);
-        cw1 = HR(h * (u - u * u));
-        cw2 = HR(u * u);
-        c0p = hist + size_t(a.slot[b]) * L;
-    }
-    const HP* bslot = nb >= 1 ? hist + size_t(a.slot[b]) * L : nullptr;
-    const HP* slot0 = nb >= 1 ? hist + size_t(a.slot[0]) * L : nullptr;
+    // Every history value is a weighted sum of two slots: Hermite in t between the
+    // bracketing stored slices; inside the current step the quadratic through the
+    // last slice with a derivative and the stage slot (weight q2 on both fields of
+    // the stage slot, which hold its value, or its FP32 value and remainder); at
+    // t = 0 the stage slot alone; with slice 0 as the only stored slice, slice 0.
+    const HP* stage = static_cast<const HP*>(a.stage);
+    const HP* bslot = nb >= 1 ? hist + size_t(a.slot[b]) * L : stage;
+    const HP* slot0 = nb >= 1 ? hist + size_t(a.slot[0]) * L : stage;
     const double hq = t - tb;
+
+    // c family: (C,R)(t', theta_i t') on this row's two slots
+    const HP* c0p;
+    const HP* c1p;
+    double cw0, cw1, cw2, cw3;
+    if (nb >= 2 && tp <= tb) {
+        const int m = bracket(s_t, 0, b, tp);
+        const double h = s_t[m + 1] - s_t[m];
+        const double u = (tp - s_t[m]) / h;
+        cw0 = 2 * u * u * u - 3 * u * u + 1;
+        cw1 = (u * u * u - 2 * u * u + u) * h;
+        cw2 = -2 * u * u * u + 3 * u * u;
+        cw3 = (u * u * u - u * u) * h;
+        c0p = hist + size_t(a.slot[m]) * L;
+        c1p = hist + size_t(a.slot[m + 1]) * L;
+    } else if (nb >= 1 && tp > tb) {
+        const double u = (tp - tb) / hq;
+        cw0 = 1.0 - u * u;
+        cw1 = hq * (u - u * u);
+        cw2 = u * u;
+        cw3 = cw2;
+        c0p = bslot;
+        c1p = stage;
+    } else if (nb == 0) {
+        cw0 = 1.0, cw1 = 1.0, cw2 = 0.0, cw3 = 0.0;
+        c0p = c1p = stage;
+    } else {
+        cw0 = 1.0, cw1 = 0.0, cw2 = 0.0, cw3 = 0.0;
+        c0p = c1p = slot0;
+    }
     const double* Xa = a.X + size_t(j) * L;          // row j, read forwards
     const double* Xb = a.X + size_t(L - 1 - j) * L;  // row L-1-j, read backwards
     const double* Xdj = a.Xd + size_t(j) * L;
@@ -375,88 +400,82 @@ __device__ __forceinline__ void hist_integral_block(const StageArgs& a, int row_
     double c0C = 0.0;
     const int i0 = cl + kColsPerWave * ph;
 #pragma unroll 1
-    for (int i = i0; i < L; i += kWave) {
+    for (int i = i0; i < L; i += kColStride) {
         const double thi = a.th[i], w = a.nu[i], xa = Xa[i], xb = Xb[L - 1 - i], xd = Xdj[i];
         double wl[S];
-        // a: (t, theta_i theta_j)
-        double aC, aR;
-        {
-            const int base = lagrange<S>(xa, L, wl);
-            interp2<S>(ysrc, base, wl, aC, aR);
-        }
-        // b: (t, phi)
         const double phi = fma(thcj, thi, thj);
-        double bC, bR;
-        {
-            const int base = lagrange<S>(double(L - 1) - xb, L, wl);
-            interp2<S>(ysrc, base, wl, bC, bR);
-        }
-        // c: (t', theta_i)
-        double cC, cR;
-        if (cmode == 2) {
-            const HP v0 = c0p[i], v1 = c1p[i];
-            cC = double(cw0 * v0.c + cw1 * v0.dc + cw2 * v1.c + cw3 * v1.dc);
-            cR = double(cw0 * v0.r + cw1 * v0.dr + cw2 * v1.r + cw3 * v1.dr);
-        } else if (cmode == 3) {
-            const HP v0 = c0p[i];
-            const YPoint yc = ysrc[i];
-            cC = double(cw0 * v0.c + cw1 * v0.dc) + double(cw2) * yc.c;
-            cR = double(cw0 * v0.r + cw1 * v0.dr) + double(cw2) * yc.r;
-        } else if (cmode == 1) {
-            const HP v = c0p[i];
-            cC = double(v.c);
-            cR = double(v.r);
-        } else {
-            const YPoint v = ysrc[i];
-            cC = v.c;
-            cR = v.r;
-        }
-        if (i == 0) c0C = cC;
-        // d: (phi t, psi)
-        double dC, dR;
-        {
-            HR wd[S];
-            const int base = lagrange<S, HR>(xd, L, wd);
-            const double s = phi * t;
-            if (nb == 0) {
-                double wy[S];
-#pragma unroll
-                for (int k = 0; k < S; ++k) wy[k] = double(wd[k]);
-                interp2<S>(ysrc, base, wy, dC, dR);
-            } else if (s <= tb) {
-                if (b == 0) {
-                    HR c, r2;
-                    interp2h<S>(slot0, base, wd, c, r2);
-                    dC = double(c);
-                    dR = double(r2);
-                } else {
+        double aC, aR, bC, bR, cC, cR, dC, dR;
+        // the stage-slice stencils and the row Hermite
+        auto fam_abc = [&]() {
+            // a: (t, theta_i theta_j)
+            {
+                const int base = lagrange<S>(xa, L, wl);
+                interp2<S>(ysrc, base, wl, aC, aR);
+            }
+            // b: (t, phi)
+            {
+                const int base = lagrange<S>(double(L - 1) - xb, L, wl);
+                interp2<S>(ysrc, base, wl, bC, bR);
+            }
+            // c: (t', theta_i)
+            {
+                const HP v0 = c0p[i], v1 = c1p[i];
+                cC = cw0 * double(v0.c) + cw1 * double(v0.dc) + cw2 * double(v1.c) + cw3 * double(v1.dc);
+                cR = cw0 * double(v0.r) + cw1 * double(v0.dr) + cw2 * double(v1.r) + cw3 * double(v1.dr);
+            }
+            if (i == 0) c0C = cC;
+        };
+        // the 2-D stencil on the history
+        auto fam_d = [&]() {
+            // d: (phi t, psi) on two slots chosen by where s = phi t falls
+            {
+                double wd[S];
+                const int base = lagrange<S>(xd, L, wd);
+                const double s = phi * t;
+                const HP* p0;
+                const HP* p1;
+                double h00, h10, h01, h11;
+                if (nb >= 2 && s <= tb) {
                     const int m = bracket_fast(s_t, s_bk, B, b, s);
                     const double h = s_t[m + 1] - s_t[m];
                     const double u = (s - s_t[m]) / h;
-                    HR c0, r0, dc0, dr0, c1, r1, dc1, dr1;
-                    interp4<S>(hist + size_t(a.slot[m]) * L, base, wd, c0, r0, dc0, dr0);
-                    // FP32 storage: values are widened as they arrive, so the second slice's
-                    // gathers wait for the first (keeps the widened values within registers)
-                    if constexpr (sizeof(HS) == 4) __builtin_amdgcn_sched_barrier(0);
-                    interp4<S>(hist + size_t(a.slot[m + 1]) * L, base, wd, c1, r1, dc1, dr1);
-                    const HR h00 = HR(2 * u * u * u - 3 * u * u + 1), h10 = HR((u * u * u - 2 * u * u + u) * h);
-                    const HR h01 = HR(-2 * u * u * u + 3 * u * u), h11 = HR((u * u * u - u * u) * h);
-                    dC = double(h00 * c0 + h10 * dc0 + h01 * c1 + h11 * dc1);
-                    dR = double(h00 * r0 + h10 * dr0 + h01 * r1 + h11 * dr1);
+                    h00 = 2 * u * u * u - 3 * u * u + 1;
+                    h10 = (u * u * u - 2 * u * u + u) * h;
+                    h01 = -2 * u * u * u + 3 * u * u;
+                    h11 = (u * u * u - u * u) * h;
+                    p0 = hist + size_t(a.slot[m]) * L;
+                    p1 = hist + size_t(a.slot[m + 1]) * L;
+                } else if (nb >= 1 && s > tb) {
+                    const double u = (s - tb) / hq;
+                    h00 = 1.0 - u * u;
+                    h10 = hq * (u - u * u);
+                    h01 = u * u;
+                    h11 = h01;
+                    p0 = bslot;
+                    p1 = stage;
+                } else if (nb == 0) {
+                    h00 = 1.0, h10 = 1.0, h01 = 0.0, h11 = 0.0;
+                    p0 = p1 = stage;
+                } else {
+                    h00 = 1.0, h10 = 0.0, h01 = 0.0, h11 = 0.0;
+                    p0 = p1 = slot0;
                 }
-            } else {
-                HR pc, pr, pdc, pdr;
-                interp4<S>(bslot, base, wd, pc, pr, pdc, pdr);
-                double wy[S];
-#pragma unroll
-                for (int k = 0; k < S; ++k) wy[k] = double(wd[k]);
-                double yc, yr;
-                interp2<S>(ysrc, base, wy, yc, yr);
-                const double u = (s - tb) / hq;
-                const double q0 = 1.0 - u * u, q1 = hq * (u - u * u), q2 = u * u;
-                dC = q0 * double(pc) + q1 * double(pdc) + q2 * yc;
-                dR = q0 * double(pr) + q1 * double(pdr) + q2 * yr;
+                double c0, r0, dc0, dr0, c1, r1, dc1, dr1;
+                interp4<S>(p0, base, wd, c0, r0, dc0, dr0);
+                // FP32 storage: values are widened as they arrive, so the second slot's
+                // gathers wait for the first (keeps the widened values within registers)
+                if constexpr (sizeof(HS) == 4) __builtin_amdgcn_sched_barrier(0);
+                interp4<S>(p1, base, wd, c1, r1, dc1, dr1);
+                dC = h00 * c0 + h10 * dc0 + h01 * c1 + h11 * dc1;
+                dR = h00 * r0 + h10 * dr0 + h01 * r1 + h11 * dr1;
             }
+        };
+        if constexpr (HistCfg<HP>::d_first) {
+            fam_d();
+            fam_abc();
+        } else {
+            fam_abc();
+            fam_d();
         }
         const double f2a = fD2<PM>(a.m, aC), f1a = fD1<PM>(a.m, aC);
         const double f2b = fD2<PM>(a.m, bC);
@@ -525,7 +544,7 @@ __device__ __forceinline__ void hist_integral_block(const StageArgs& a, int row_
 
 // One instance: the stage arguments travel by value.
 template <int S, int PM, class HP, bool YL>
-__global__ __launch_bounds__(kRowsPerBlock * 64) void k_hist_integral(const StageArgs a) {
+__global__ __launch_bounds__(hist_threads<HP>()) void k_hist_integral(const StageArgs a) {
     hist_integral_block<S, PM, HP, YL>(a, blockIdx.x);
 }
 
@@ -533,7 +552,7 @@ __global__ __launch_bounds__(kRowsPerBlock * 64) void k_hist_integral(const Stag
 // with first_block[q] <= b < first_block[q+1]; instances may differ in L, M,
 // t and history.  The dynamic LDS is sized for the largest nb of the batch.
 template <int S, int PM, class HP, bool YL>
-__global__ __launch_bounds__(kRowsPerBlock * 64) void k_hist_integral_multi(const StageArgs* __restrict__ args,
+__global__ __launch_bounds__(hist_threads<HP>()) void k_hist_integral_multi(const StageArgs* __restrict__ args,
                                                                             const int* __restrict__ first_block,
                                                                             int n_inst) {
     int lo = 0, hi = n_inst;  // first_block[lo] <= b < first_block[hi]
@@ -768,9 +787,11 @@ hipError_t launch_coords(const GridArgs& g, hipStream_t st) {
 }
 
 hipError_t launch_stage_prep(const Model& m, int L, double t, const double* nu, const YPoint* y, double* mue,
-                             hipStream_t st) {
-    if (m.pmax <= 4) hipLaunchKernelGGL(k_stage_prep<4>, dim3(1), dim3(1024), 0, st, m, L, t, nu, y, mue);
-    else hipLaunchKernelGGL(k_stage_prep<DMFE_MAX_P>, dim3(1), dim3(1024), 0, st, m, L, t, nu, y, mue);
+                             void* stage, int fp32, hipStream_t st) {
+    if (m.pmax <= 4)
+        hipLaunchKernelGGL(k_stage_prep<4>, dim3(1), dim3(1024), 0, st, m, L, t, nu, y, mue, stage, fp32);
+    else
+        hipLaunchKernelGGL(k_stage_prep<DMFE_MAX_P>, dim3(1), dim3(1024), 0, st, m, L, t, nu, y, mue, stage, fp32);
     return hipGetLastError();
 }
 
@@ -796,7 +817,7 @@ static void allow_lds(K kernel, size_t bytes) {
 
 template <int S, class HP, bool YL>
 static void launch_hi_shy(const StageArgs& a, size_t lds, hipStream_t st) {
-    const dim3 grid(nblk(a.L, kRowsPerBlock)), block(kRowsPerBlock * kWave);
+    const dim3 grid(nblk(a.L, kRowsPerBlock)), block(hist_threads<HP>());
     if (a.m.pmax <= 4) {
         allow_lds(k_hist_integral<S, 4, HP, YL>, lds);
         hipLaunchKernelGGL((k_hist_integral<S, 4, HP, YL>), grid, block, lds, st, a);
@@ -807,9 +828,9 @@ static void launch_hi_shy(const StageArgs& a, size_t lds, hipStream_t st) {
 }
 template <int S, class HP>
 static hipError_t launch_hi_sh(const StageArgs& a, hipStream_t st) {
-    const size_t with_y = lds_bytes(a.nb, a.L, true);
+    const size_t with_y = lds_bytes<HP>(a.nb, a.L, true);
     if (with_y <= max_lds()) launch_hi_shy<S, HP, true>(a, with_y, st);
-    else launch_hi_shy<S, HP, false>(a, lds_bytes(a.nb, a.L, false), st);
+    else launch_hi_shy<S, HP, false>(a, lds_bytes<HP>(a.nb, a.L, false), st);
     return hipGetLastError();
 }
 template <int S>
@@ -954,20 +975,21 @@ static void hist_multi_launch(const StageArgs* d, const int* fb, int n, int bloc
     allow_lds(k_hist_integral_multi<S, 4, HP, false>, lds);
     allow_lds(k_hist_integral_multi<S, DMFE_MAX_P, HP, false>, lds);
     if (pmax <= 4)
-        hipLaunchKernelGGL((k_hist_integral_multi<S, 4, HP, false>), dim3(blocks), dim3(kRowsPerBlock * kWave), lds,
+        hipLaunchKernelGGL((k_hist_integral_multi<S, 4, HP, false>), dim3(blocks), dim3(hist_threads<HP>()), lds,
                            st, d, fb, n);
     else
         hipLaunchKernelGGL((k_hist_integral_multi<S, DMFE_MAX_P, HP, false>), dim3(blocks),
-                           dim3(kRowsPerBlock * kWave), lds, st, d, fb, n);
+                           dim3(hist_threads<HP>()), lds, st, d, fb, n);
 }
 
 hipError_t launch_hist_integral_multi(const StageArgs* d, const int* first_block, int n, int total_blocks, int s,
                                       int pmax, int fp32, int nb_max, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    const size_t lds = lds_bytes(nb_max, 0, false);
     if (s != 10) return hipErrorInvalidValue;  // the pool serves the default stencil
-    if (fp32) hist_multi_launch<10, HPoint32>(d, first_block, n, total_blocks, pmax, lds, st);
-    else hist_multi_launch<10, HPoint>(d, first_block, n, total_blocks, pmax, lds, st);
+    if (fp32)
+        hist_multi_launch<10, HPoint32>(d, first_block, n, total_blocks, pmax, lds_bytes<HPoint32>(nb_max, 0, false), st);
+    else
+        hist_multi_launch<10, HPoint>(d, first_block, n, total_blocks, pmax, lds_bytes<HPoint>(nb_max, 0, false), st);
     return hipGetLastError();
 }
 

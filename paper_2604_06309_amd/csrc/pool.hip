@@ -237,7 +237,9 @@ dmfe_status tick(dmfe_pool* P) {
             pd.y = ycur;
             pd.nu = h->at<double>(h->lo.nu);
             pd.mue = h->at<double>(h->lo.mue);
+            pd.stage = stage_slot(h);
             pd.L = L;
+            pd.fp32 = h->fp32;
             pd.t = tst;
             pd.m = h->m;
             a_args[n_eval] = stage_args(h, tst, nb, ycur, kst, store);

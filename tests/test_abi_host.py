@@ -157,7 +157,8 @@ def test_sparsify_select_matches_oracle(lib):
 def test_footprint(lib):
     p = pk.make_params({3: 0.5, 4: 0.5}, 0.55, t_max=1e7, L=4096)
     fp = pk.dmfe_footprint(p)
-    hist, coords = 4096 * 4096 * 32, 2 * 4096 * 4096 * 8  # history slots + the two coordinate tables
+    # history slots (M_cap = L, plus the stage slot) and the two coordinate tables
+    hist, coords = (4096 + 1) * 4096 * 32, 2 * 4096 * 4096 * 8
     assert hist + coords <= fp < (hist + coords) * 1.01
     p32 = pk.make_params({3: 0.5, 4: 0.5}, 0.55, t_max=1e7, L=4096, precision=pk.FP32_COMP)
     assert fp - pk.dmfe_footprint(p32) == hist // 2

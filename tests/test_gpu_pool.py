@@ -83,3 +83,37 @@ def test_pool_rejects_what_cannot_fit():
         pool.submit(p)
     assert e.value.status == pk.ERR_NOMEM
     pool.close()
+
+
+@pytest.mark.parametrize("precision", [pk.FP64, pk.FP32_COMP])
+def test_sixteen_large_instances_stepped_together(precision):
+    """The large-grid stress case: 16 identical solves of the 2+4 model (a2^2 = 0.3,
+    a4^2 = 0.7, T = 0.45, t_max = 1e7) on a 8192-point grid with history cap 8192,
+    all admitted at once and stepped together in batched launches.  After the
+    same number of ticks every instance holds bitwise the same history, equal to
+    the same solve run alone for the same number of steps."""
+    say(f"16 instances at L=8192, precision={precision}")
+    p = pk.make_params({2: 0.3, 4: 0.7}, 0.45, t_max=1e7, L=8192, M_cap=8192, eps=1e-8, dt0=1e-3, dt_min=1e-12,
+                       precision=precision)
+    fp = pk.dmfe_footprint(p)
+    pool = pk.Pool(16 * fp + 4096, max_instances=16)
+    ids = [pool.submit(p) for _ in range(16)]
+    st = pool.run(6 * 25)
+    assert st.running == 16 and st.queued == 0
+    infos = [pool.result(rid)[0] for rid in ids]
+    steps = infos[0].accepted + infos[0].rejected
+    assert steps >= 20 and all((i.accepted, i.rejected, i.M, i.t) == (infos[0].accepted, infos[0].rejected,
+                                                                        infos[0].M, infos[0].t) for i in infos)
+    ref = [pool.read(ids[0], f, L=8192) for f in (pk.F_T_GRID, pk.F_C, pk.F_R)]
+    for rid in ids[1:]:
+        for f, r in zip((pk.F_T_GRID, pk.F_C, pk.F_R), ref):
+            np.testing.assert_array_equal(pool.read(rid, f, L=8192), r)
+    pool.close()
+    s = pk.Solver(p)
+    _, info = s.step(float("inf"), steps)
+    assert (info.accepted, info.rejected, info.M) == (infos[0].accepted, infos[0].rejected, infos[0].M)
+    np.testing.assert_array_equal(s.read(pk.F_T_GRID), ref[0])
+    np.testing.assert_array_equal(s.read(pk.F_C), ref[1])
+    np.testing.assert_array_equal(s.read(pk.F_R), ref[2])
+    s.close()
+    say(f"  16 instances bitwise equal to each other and to the solo solve after {steps} steps, M={info.M}")

@@ -13,7 +13,9 @@ device synchronisations.  Per-kernel durations are HIP events recorded by the
 library on its own stream during (3).  The line's value is the --precision
 solve (FP64 by default); the same three phases then run for the other
 precision (FP32-compensated history by default) and are reported beside it.
-Then come the serving sweep and the CPU baseline (the oracle).
+Then come the end-to-end run of the uniform-grid configuration (p=3, N=1000,
+with the oracle timed beside it), the serving sweep and the CPU baseline (the
+oracle).  --c2 adds the L=2048 configuration from t=0 to t_max=1e4.
 
 One JSON line is printed on stdout; progress goes to stderr.
 """
@@ -246,6 +248,60 @@ def kernel_bench(pk, args) -> dict:
             "achieved_GBps": alg / (avg_us * 1e-6) / 1e9, "calibration_copies": cal}
 
 
+def uniform_c1(pk, torch, with_oracle: bool) -> dict:
+    """The uniform-grid baseline: pure p=3 (f = q^3/2), T = 0.5, h = 0.05, N = 1000
+    (t_max = 50), classical RK4 with trapezoid history integrals.  Time to
+    solution of the library (4000 stages), and of the oracle on the host."""
+    p = pk.make_params({3: 1.0}, 0.5, mode=pk.UNIFORM, h=0.05, N=1000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s = pk.Solver(p)
+    s.step(float("inf"))
+    torch.cuda.synchronize()
+    gpu_s = time.perf_counter() - t0
+    E = s.read(pk.F_ENERGY)
+    s.close()
+    out = {"config": "p=3, T=0.5, h=0.05, N=1000, RK4 + trapezoid (uniform grid)", "gpu_s": gpu_s,
+           "E_final": float(E[-1])}
+    if with_oracle:
+        import oracle
+        t0 = time.perf_counter()
+        _, _, Eo = oracle.uniform_solve(oracle.make_model({3: 1.0}, T=0.5), 0.05, 1000)
+        out["oracle_s"] = time.perf_counter() - t0
+        out["oracle_threads"] = oracle.num_threads()
+        out["max_abs_dE_vs_oracle"] = float(abs(Eo - E).max())
+    log(f"C1 uniform: GPU {gpu_s:.2f} s" + (f", oracle {out['oracle_s']:.2f} s" if with_oracle else ""))
+    return out
+
+
+def adaptive_c2(pk, torch) -> dict:
+    """The L = 2048 workload end to end: 3+4 model, T = 0.6, t_max = 1e4, eps = 1e-8,
+    FP64, from t = 0 to t_max, with M(t) sampled every 2000 steps.  The history
+    capacity is 8192 slices (0.54 GB): at this tolerance the sparsified history
+    needs about 2048 slices by t = 1800 and keeps growing."""
+    p = pk.make_params({3: 0.5, 4: 0.5}, 0.6, t_max=1e4, L=2048, M_cap=8192, eps=1e-8, dt0=1e-3, dt_min=1e-12)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s = pk.Solver(p)
+    trace = []
+    while True:
+        st, info = s.step(float("inf"), 2000)
+        trace.append([int(info.accepted + info.rejected), float(info.t), int(info.M), round(time.perf_counter() - t0, 2)])
+        log(f"C2: steps={trace[-1][0]} t={info.t:.5g} M={info.M} dt={info.dt:.3g} scheme={info.scheme}")
+        if st == pk.DONE:
+            break
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    E = s.read(pk.F_ENERGY)
+    s.close()
+    steps = info.accepted + info.rejected
+    return {"config": "3+4, T=0.6, t_max=1e4, L=2048, history cap 8192, eps=1e-8, FP64", "wall_s": wall,
+            "steps": int(steps), "accepted": int(info.accepted), "rejected": int(info.rejected),
+            "steps_per_s": steps / wall, "rhs_evals": int(info.rhs_evals), "sparsify_calls": int(info.sparsify_calls),
+            "removed": int(info.removed), "M_final": int(info.M), "t_final": info.t, "scheme_final": int(info.scheme),
+            "E_final": float(E[-1]), "trace_steps_t_M_wall": trace}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -255,6 +311,9 @@ def main() -> int:
     ap.add_argument("--fill-seconds", type=float, default=150.0, help="time budget of the untimed fill phase")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the timed window at the other precision")
+    ap.add_argument("--no-configs", action="store_true", help="skip the end-to-end run of the uniform-grid configuration")
+    ap.add_argument("--c2", action="store_true",
+                    help="also run the L=2048 configuration from t=0 to t_max=1e4 (about 40,000 steps, 75 s)")
     ap.add_argument("--serving", type=int, default=24, help="requests in the serving sweep (0: skip)")
     ap.add_argument("--kernel", action="store_true",
                     help="time the history-integral kernel alone on a synthetic full-size history")
@@ -304,6 +363,10 @@ def main() -> int:
                       "rhs_evals_per_step": o["config"]["rhs_evals_per_step"],
                       "hist_integral_avg_launch_us": o["roofline"]["avg_launch_us"],
                       "roofline": o["roofline"]}
+    if not args.no_configs:
+        out["c1_uniform"] = uniform_c1(pk, torch, with_oracle=not args.no_cpu_baseline)
+    if args.c2:
+        out["c2_adaptive"] = adaptive_c2(pk, torch)
     if args.serving > 0:
         out["serving"] = serving_sweep(pk, args.serving)
     if not args.no_cpu_baseline:

@@ -85,7 +85,8 @@ def hist_integral_bytes(L: int, slices: float, fp32: bool = False) -> float:
 
 def cpu_baseline(L: int, M: int, evals_per_step: float, budget_s: float = 20.0):
     """The oracle's right-hand side on a synthetic history of the same shape,
-    timed on a sample of rows and scaled to one RK step."""
+    timed over the rows of up to one RK step's evaluations (about 10-20 s of
+    host work at L = 4096) and scaled to one RK step."""
     import numpy as np
 
     import oracle
@@ -104,19 +105,20 @@ def cpu_baseline(L: int, M: int, evals_per_step: float, budget_s: float = 20.0):
     yR = np.exp(-1.3 * k * t * ts.thc)
     threads = oracle.num_threads()
     done, elapsed, nrows = 0, 0.0, 16
-    order = rng.permutation(L)
-    while done < L and elapsed < budget_s:
-        rows = order[done:done + nrows]
+    target = int(round(evals_per_step * L))
+    order = np.tile(rng.permutation(L), int(np.ceil(evals_per_step)) + 1)
+    while done < target and elapsed < budget_s:
+        rows = order[done:min(done + nrows, target)]
         t0 = time.perf_counter()
         oracle.theta_rhs(m, ts, times, C, R, dC, dR, M, t, yC, yR, rows=rows)
         elapsed += time.perf_counter() - t0
         done += rows.size
-        nrows *= 2
+        nrows = min(nrows * 2, L)
         log(f"cpu baseline: {done} rows in {elapsed:.1f} s")
     per_eval = elapsed / done * L
     return {"value": 1.0 / (per_eval * evals_per_step), "unit": "steps/s", "cores": threads, "kind": "oracle",
-            "sample": f"{done} of {L} rows of one right-hand-side evaluation at L={L}, M={M} "
-                      f"(synthetic smooth history), scaled to {evals_per_step:.2f} evaluations per step"}
+            "sample": f"{done} rows ({done / L:.2f} right-hand-side evaluations) at L={L}, M={M} "
+                      f"(synthetic smooth history), {elapsed:.1f} s, scaled to {evals_per_step:.2f} evaluations per step"}
 
 
 def sweep_requests(pk, n: int, seed: int, precision: int, tmax_range=(10.0, 100.0)):

@@ -241,6 +241,30 @@ const char *dmfe_status_string(dmfe_status s);
 /* Text of the last HIP failure seen by any handle in this thread ("" if none). */
 const char *dmfe_last_error(void);
 
+/* ---------------------------------------------------------------- checkpoint and resume
+ * Long solves (Sec. 4: runs to t ~ 1e7) survive restarts.  A checkpoint holds
+ * the parameters (the solve's record), the controller state and counters, the
+ * stored history in logical order, the FP64 state y(t) and, for DP5, the last
+ * stage derivative it reuses, so a restored handle continues bitwise as the
+ * saved one would have.  Adaptive mode only (DMFE_ERR_UNSUPPORTED otherwise).
+ */
+
+/* Save h's state to the file `path` (host string).  The device state is copied
+ * to host memory before the call returns (the handle may step on at once);
+ * with async != 0 the file is written by a background thread.  At most one
+ * write is in flight per handle: a save first waits for the previous one and
+ * returns its error, if any.  Not allowed while a pool steps the handle.
+ * Errors: DMFE_ERR_INVALID (bad arguments, file cannot be written),
+ * DMFE_ERR_DEVICE. */
+dmfe_status dmfe_checkpoint_save(dmfe_handle *h, const char *path, int32_t async);
+/* Wait for h's checkpoint write in flight, if any; returns its status. */
+dmfe_status dmfe_checkpoint_wait(dmfe_handle *h);
+/* Create a handle from the checkpoint file `path` on the device and stream of
+ * `res` (as dmfe_create; a caller workspace must be at least dmfe_footprint of
+ * the saved parameters).  DMFE_ERR_INVALID if the file is missing, of another
+ * format or version, inconsistent, truncated or fails its checksum. */
+dmfe_status dmfe_checkpoint_load(const char *path, const dmfe_resources *res, dmfe_handle **out);
+
 /* ---------------------------------------------------------------- serving pool
  * Many solves (a parameter sweep: different T, a_p, t_max, L) stepped
  * together on one device.  Requests queue on submit and are admitted while a

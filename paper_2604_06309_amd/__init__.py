@@ -99,6 +99,9 @@ SIGNATURES = {
     "dmfe_control_update": (_i32, [ctypes.POINTER(dmfe_control), _d, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "dmfe_sparsify_select": (_i32, [_vp, _i64, _i64, _d, _vp, ctypes.POINTER(_i64)]),
     "dmfe_timing": (_i32, [_vp, _i32]),
+    "dmfe_checkpoint_save": (_i32, [_vp, ctypes.c_char_p, _i32]),
+    "dmfe_checkpoint_wait": (_i32, [_vp]),
+    "dmfe_checkpoint_load": (_i32, [ctypes.c_char_p, ctypes.POINTER(dmfe_resources), ctypes.POINTER(_vp)]),
     "dmfe_pool_create": (_i32, [ctypes.POINTER(dmfe_pool_params), ctypes.POINTER(dmfe_resources),
                                 ctypes.POINTER(_vp)]),
     "dmfe_pool_submit": (_i32, [_vp, ctypes.POINTER(dmfe_params), ctypes.POINTER(ctypes.c_uint64)]),
@@ -253,6 +256,23 @@ def dmfe_timing_read(h: int, kernel: int) -> tuple[int, float, int]:
 def dmfe_destroy(h: int) -> None:
     if h:
         lib().dmfe_destroy(h)
+
+
+def dmfe_checkpoint_save(h: int, path: str, async_write: bool = False) -> None:
+    _check(lib().dmfe_checkpoint_save(h, os.fsencode(path), int(async_write)), "dmfe_checkpoint_save")
+
+
+def dmfe_checkpoint_wait(h: int) -> None:
+    _check(lib().dmfe_checkpoint_wait(h), "dmfe_checkpoint_wait")
+
+
+def dmfe_checkpoint_load(path: str, device: int = 0, stream: int = 0, workspace: int = 0,
+                         workspace_bytes: int = 0) -> int:
+    r = dmfe_resources()
+    r.device, r.stream, r.workspace, r.workspace_bytes = device, stream or None, workspace or None, workspace_bytes
+    h = ctypes.c_void_p()
+    _check(lib().dmfe_checkpoint_load(os.fsencode(path), ctypes.byref(r), ctypes.byref(h)), "dmfe_checkpoint_load")
+    return h.value
 
 
 def dmfe_status_string(status: int) -> str:
@@ -411,6 +431,26 @@ class Solver:
             self._ws = torch.empty(nbytes, dtype=torch.uint8, device=f"cuda:{dev}")
             ws, wsb = self._ws.data_ptr(), nbytes
         self.h = dmfe_create(params, dev, self.stream.cuda_stream, ws, wsb)
+
+    @classmethod
+    def load(cls, path: str, params: dmfe_params, device: Optional[int] = None, stream=None) -> "Solver":
+        """Restore a solver from a checkpoint file written by checkpoint(); `params`
+        must be the saved solve's parameters (they size the handle's view)."""
+        import torch
+        self = cls.__new__(cls)
+        lib()
+        self.params = params
+        dev = torch.cuda.current_device() if device is None else device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        self._ws = None
+        self.h = dmfe_checkpoint_load(path, dev, self.stream.cuda_stream)
+        return self
+
+    def checkpoint(self, path: str, async_write: bool = False) -> None:
+        dmfe_checkpoint_save(self.h, path, async_write)
+
+    def checkpoint_wait(self) -> None:
+        dmfe_checkpoint_wait(self.h)
 
     def close(self):
         if getattr(self, "h", None):

@@ -216,6 +216,10 @@ dmfe_status fail(hipError_t e, const char* what) {
     set_error(std::string(what) + ": " + hipGetErrorString(e));
     return DMFE_ERR_DEVICE;
 }
+dmfe_status fail_msg(dmfe_status s, const std::string& msg) {
+    set_error(msg);
+    return s;
+}
 
 // Event pair around one launch when timing is on; nullptr otherwise.
 dmfe_handle::EvPair* timing_begin(dmfe_handle* h, int kernel, int64_t slices) {
@@ -783,6 +787,7 @@ dmfe_status dmfe_create(const dmfe_params* params, const dmfe_resources* res, dm
 
 void dmfe_destroy(dmfe_handle* h) {
     if (!h) return;
+    ckpt_release(h);
     (void)hipSetDevice(h->device);
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     else (void)hipDeviceSynchronize();

@@ -31,6 +31,8 @@ struct Layout {
 constexpr double kDp5Limit = 3.3065;
 constexpr double kSspLimit = 13.917;
 
+struct CkptWriter;  // background checkpoint writer (checkpoint.hip)
+
 }  // namespace core
 }  // namespace dmfe
 
@@ -83,6 +85,8 @@ struct dmfe_handle {
         int next_slot = -1;
     } cur;
 
+    dmfe::core::CkptWriter* ckpt = nullptr;  // at most one checkpoint write in flight
+
     template <class T> T* at(size_t off) const { return reinterpret_cast<T*>(base + off); }
 };
 
@@ -93,6 +97,9 @@ namespace core {
 void set_error(const std::string& msg);
 const char* last_error();
 dmfe_status fail(hipError_t e, const char* what);
+dmfe_status fail_msg(dmfe_status s, const std::string& msg);  // records msg, returns s
+dmfe_status ckpt_join(dmfe_handle* h);   // waits for the handle's checkpoint write, returns its status
+void ckpt_release(dmfe_handle* h);       // waits for it and frees the writer
 #define HCHK(expr)                                            \
     do {                                                      \
         hipError_t e_ = (expr);                               \

@@ -164,3 +164,18 @@ def test_footprint(lib):
     assert fp - pk.dmfe_footprint(p32) == hist // 2
     pu = pk.make_params({3: 1.0}, 0.5, mode=pk.UNIFORM, h=0.05, N=1000)
     assert pk.dmfe_footprint(pu) >= 2 * 1001 * 1002 // 2 * 8
+
+
+def test_checkpoint_load_rejects_bad_files(lib, tmp_path):
+    """Loading fails cleanly, before any device work, on a missing file, a file of
+    another kind, and a checkpoint whose payload was altered."""
+    missing = tmp_path / "none.ckpt"
+    with pytest.raises(pk.DmfeError) as e:
+        pk.dmfe_checkpoint_load(str(missing))
+    assert e.value.status == pk.ERR_INVALID
+    junk = tmp_path / "junk.ckpt"
+    junk.write_bytes(b"not a checkpoint" * 64)
+    with pytest.raises(pk.DmfeError) as e:
+        pk.dmfe_checkpoint_load(str(junk))
+    assert e.value.status == pk.ERR_INVALID
+    assert "checkpoint" in pk.dmfe_last_error()

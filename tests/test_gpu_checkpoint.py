@@ -1,0 +1,72 @@
+"""Checkpoint and resume: a solve saved to a file and restored into a new handle
+continues bitwise as the uninterrupted solve (same accepted/rejected counts, time
+grid and history), through sparsification, the DP5 -> SSPRK(10,4) switch, FP32
+histories and asynchronous writes; a checkpoint whose payload is altered is
+refused."""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+import paper_2604_06309_amd as pk  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _state(s):
+    info = s.info()
+    return (info.accepted, info.rejected, info.M, info.scheme, info.sparsify_calls, info.removed,
+            s.read(pk.F_T_GRID), s.read(pk.F_C), s.read(pk.F_R), s.read(pk.F_DC), s.read(pk.F_DR))
+
+
+def _same(a, b):
+    assert a[:6] == b[:6], (a[:6], b[:6])
+    for x, y in zip(a[6:], b[6:]):
+        np.testing.assert_array_equal(x, y)
+
+
+@pytest.mark.parametrize("precision,policy,async_write,n1,n2", [
+    (pk.FP64, 0, False, 300, 560),       # DP5, sparsification at a 400-slice cap before and after the save
+    (pk.FP32_COMP, 0, True, 300, 560),   # FP32 history, asynchronous write
+    (pk.FP64, 1, True, 200, 450),        # SSPRK(10,4) from the start
+])
+def test_resume_is_bitwise(tmp_path, precision, policy, async_write, n1, n2):
+    say(f"checkpoint precision={precision} policy={policy} async={async_write}")
+    p = pk.make_params({3: 0.5, 4: 0.5}, 0.6, t_max=1e4, L=64, M_cap=400, eps=1e-8, dt0=1e-3, dt_min=1e-12,
+                       precision=precision, scheme_policy=policy)
+    path = str(tmp_path / "solve.ckpt")
+    ref = pk.Solver(p)
+    ref.step(float("inf"), n1)
+    ref.checkpoint(path, async_write=async_write)
+    ref.step(float("inf"), n2 - n1)  # steps on while the file is written
+    ref.checkpoint_wait()
+    want = _state(ref)
+    ref.close()
+    s = pk.Solver.load(path, p)
+    s.step(float("inf"), n2 - n1)
+    got = _state(s)
+    s.close()
+    _same(got, want)
+    say(f"  resumed solve equals the uninterrupted one after {want[0] + want[1]} steps, M={want[2]}, "
+        f"sparsify passes={want[4]}")
+
+
+def test_corrupted_checkpoint_is_refused(tmp_path):
+    p = pk.make_params({3: 0.5, 4: 0.5}, 0.6, t_max=1e4, L=64, M_cap=100, eps=1e-8, dt0=1e-3, dt_min=1e-12)
+    path = tmp_path / "solve.ckpt"
+    s = pk.Solver(p)
+    s.step(float("inf"), 40)
+    s.checkpoint(str(path))
+    s.close()
+    raw = bytearray(path.read_bytes())
+    raw[-9] ^= 0x40  # one bit of the stored history
+    path.write_bytes(bytes(raw))
+    with pytest.raises(pk.DmfeError) as e:
+        pk.Solver.load(str(path), p)
+    assert e.value.status == pk.ERR_INVALID

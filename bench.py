@@ -15,7 +15,8 @@ solve (FP64 by default); the same three phases then run for the other
 precision (FP32-compensated history by default) and are reported beside it.
 Then come the end-to-end run of the uniform-grid configuration (p=3, N=1000,
 with the oracle timed beside it), the serving sweep and the CPU baseline (the
-oracle).  --c2 adds the L=2048 configuration from t=0 to t_max=1e4.
+oracle).  --c2 adds the L=2048 configuration from t=0 to t_max=1e4, --aging
+the paper's energy-exponent experiment (pure p=3 quenched to T=0).
 
 One JSON line is printed on stdout; progress goes to stderr.
 """
@@ -304,6 +305,31 @@ def adaptive_c2(pk, torch) -> dict:
             "E_final": float(E[-1]), "trace_steps_t_M_wall": trace}
 
 
+def aging_p3(pk, torch, t_end: float = 1e4) -> dict:
+    """The paper's energy-exponent experiment (Sec. 4.2): pure p=3 (f = q^3/2),
+    quench from a random start to T = 0, L = 1024, eps = 1e-10, to t_end.  Reports
+    E(t) - E_th at quarter decades of t and the effective exponent between them."""
+    import numpy as np
+    p = pk.make_params({3: 1.0}, 0.0, t_max=1e7, L=1024, M_cap=8192, eps=1e-10, dt0=1e-3, dt_min=1e-14)
+    E_th = -np.sqrt(4.0 / 3.0)
+    t0 = time.perf_counter()
+    s = pk.Solver(p)
+    rows, t_next = [], 1.0
+    while t_next <= t_end * 1.001:
+        _, info = s.step(t_next)
+        E = float(s.read(pk.F_ENERGY)[-1])
+        rows.append([info.t, E, E - E_th, int(info.accepted + info.rejected), int(info.M)])
+        log(f"aging: t={info.t:.5g} E-E_th={E - E_th:.4e} steps={rows[-1][3]} M={info.M}")
+        t_next *= 10 ** 0.25
+    s.close()
+    t = np.array([r[0] for r in rows])
+    d = np.array([r[2] for r in rows])
+    alpha = (-np.diff(np.log(d)) / np.diff(np.log(t))).tolist()
+    return {"config": "pure p=3 (f=q^3/2), T=0 after a random start, L=1024, eps=1e-10, history cap 8192",
+            "E_th": E_th, "wall_s": time.perf_counter() - t0, "rows_t_E_dE_steps_M": rows,
+            "alpha_eff_between_rows": alpha}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -314,6 +340,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the timed window at the other precision")
     ap.add_argument("--no-configs", action="store_true", help="skip the end-to-end run of the uniform-grid configuration")
+    ap.add_argument("--aging", action="store_true",
+                    help="also run the energy-exponent experiment (pure p=3 quenched to T=0, to t=1e4, about 50 s)")
     ap.add_argument("--c2", action="store_true",
                     help="also run the L=2048 configuration from t=0 to t_max=1e4 (about 40,000 steps, 75 s)")
     ap.add_argument("--serving", type=int, default=24, help="requests in the serving sweep (0: skip)")
@@ -369,6 +397,8 @@ def main() -> int:
         out["c1_uniform"] = uniform_c1(pk, torch, with_oracle=not args.no_cpu_baseline)
     if args.c2:
         out["c2_adaptive"] = adaptive_c2(pk, torch)
+    if args.aging:
+        out["aging_p3"] = aging_p3(pk, torch)
     if args.serving > 0:
         out["serving"] = serving_sweep(pk, args.serving)
     if not args.no_cpu_baseline:

@@ -40,7 +40,12 @@ class Model(ctypes.Structure):
 
 class Grid(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int), ("s", ctypes.c_int), ("gamma", ctypes.c_double), ("D", ctypes.c_double),
-                ("th", ctypes.c_void_p), ("thc", ctypes.c_void_p), ("nu", ctypes.c_void_p)]
+                ("th", ctypes.c_void_p), ("thc", ctypes.c_void_p), ("nu", ctypes.c_void_p),
+                ("interp", ctypes.c_int), ("fh_d", ctypes.c_int), ("log_r", ctypes.c_int), ("pad", ctypes.c_int)]
+
+
+# theta-interpolation schemes (Sec. 3.3)
+INDEX_LAGRANGE, THETA_LAGRANGE, INDEX_FH, THETA_FH = 0, 1, 2, 3
 
 
 class Hist(ctypes.Structure):
@@ -93,7 +98,7 @@ def lib():
         _lib.or_mu_energy.argtypes = [ctypes.POINTER(Model), i, vp, d, vp, vp, vp, vp]
         _lib.or_theta_rhs.argtypes = [ctypes.POINTER(Model), ctypes.POINTER(Grid), ctypes.POINTER(Hist), d,
                                       vp, i, vp, vp, vp]
-        _lib.or_hist_value.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Hist), d, i, d, vp]
+        _lib.or_hist_value.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Hist), d, i, d, d, d, vp]
         _lib.or_sparsify_residuals.argtypes = [i, i, vp, vp, vp, vp, vp, vp]
         _lib.or_sparsify_select.restype = i
         _lib.or_sparsify_select.argtypes = [i, i, vp, d, vp]
@@ -203,10 +208,16 @@ def quad_weights(th: np.ndarray) -> np.ndarray:
 
 
 class ThetaSetup:
-    """The run-constant theta-grid data of the oracle: theta, 1-theta, nu, gamma."""
+    """The run-constant theta-grid data of the oracle: theta, 1-theta, nu, gamma,
+    and the theta-interpolation scheme: `interp` (INDEX_LAGRANGE, THETA_LAGRANGE,
+    INDEX_FH, THETA_FH) on s-point stencils, the Floater-Hormann degree `fh_d`,
+    and `log_r` (interpolate log R, Appendix A)."""
 
-    def __init__(self, L: int, tmax: float, s: int = 10):
+    def __init__(self, L: int, tmax: float, s: int = 10, interp: int = INDEX_LAGRANGE, fh_d: int = 3,
+                 log_r: bool = False):
+        assert 2 <= s <= 16 and 0 <= fh_d <= s - 1
         self.L, self.s, self.tmax = L, s, tmax
+        self.interp, self.fh_d, self.log_r = interp, fh_d, bool(log_r)
         self.gamma = gamma_of(tmax)
         self.th, self.thc = theta_grid(L, tmax)
         self.nu = quad_weights(self.th)
@@ -214,6 +225,7 @@ class ThetaSetup:
         self.grid.L, self.grid.s, self.grid.gamma = L, s, self.gamma
         self.grid.D = float(np.arctan(np.exp(self.gamma)) - np.arctan(np.exp(-self.gamma)))
         self.grid.th, self.grid.thc, self.grid.nu = _p(self.th), _p(self.thc), _p(self.nu)
+        self.grid.interp, self.grid.fh_d, self.grid.log_r = int(interp), int(fh_d), int(bool(log_r))
 
 
 def mu_energy(m: Model, ts: ThetaSetup, t: float, yC: np.ndarray, yR: np.ndarray):
@@ -259,12 +271,36 @@ def theta_rhs(m: Model, ts: ThetaSetup, t_hist, C, R, dC, dR, nb: int, t: float,
     return outC, outR, mu, sums
 
 
-def hist_value(ts: ThetaSetup, t_hist, C, R, dC, dR, nb, t, yC, yR, tau, node=-1, x=0.0):
+def hist_value(ts: ThetaSetup, t_hist, C, R, dC, dR, nb, t, yC, yR, tau, node=-1, x=0.0, th=None, thc=None):
+    """(C, R) at time tau and the grid node `node`, or (node < 0) at the point of
+    continuous index x; the theta schemes also need its theta and 1 - theta
+    (default: from x through the grid map)."""
     keep: list = []
     H = _hist(t_hist, C, R, dC, dR, nb, t, yC, yR, keep)
+    if node < 0 and th is None:
+        th, thc = theta_at_index(ts, x)
+    if th is None:
+        th, thc = 0.0, 1.0
+    if thc is None:
+        thc = 1.0 - th
     out = np.zeros(2)
-    lib().or_hist_value(ctypes.byref(ts.grid), ctypes.byref(H), tau, node, x, _p(out))
+    lib().or_hist_value(ctypes.byref(ts.grid), ctypes.byref(H), tau, node, x, float(th), float(thc), _p(out))
     return out
+
+
+def theta_at_index(ts: ThetaSetup, x: float):
+    """theta and 1 - theta at continuous index x (eq. theta at alpha = 0, the
+    0-based index i taken as continuous)."""
+    L, g = ts.L, ts.gamma
+    y = (2.0 * x + 1.0 - L) / (L - 1)
+    y = min(max(y, -1.0), 1.0)
+    def lower(yy):  # theta(yy) for yy <= 0, full relative precision
+        return np.arctan(np.sinh(0.5 * g * (1.0 + yy)) / np.cosh(0.5 * g * (1.0 - yy))) / np.arctan(np.sinh(g))
+    if y <= 0.0:
+        th = float(lower(y))
+        return th, 1.0 - th
+    thc = float(lower(-y))
+    return 1.0 - thc, thc
 
 
 # ----------------------------------------------------------------------------- sparsify

@@ -15,8 +15,10 @@
  *     Sec. 2.3; the scheme itself is not printed in the paper, see the
  *     readings list in the design notes);
  *   - the theta-grid of eq. (theta) at alpha = 0 and its inverse index map;
- *   - one evaluation of the right-hand side on the theta-grid: index-space
- *     Lagrange interpolation in theta (Sec. 3.3), cubic Hermite interpolation
+ *   - one evaluation of the right-hand side on the theta-grid: interpolation
+ *     in theta by one of the schemes of Sec. 3.3 (Lagrange on the index
+ *     coordinate -- the default -- or on theta, Floater-Hormann on either),
+ *     optionally on log R (Appendix A), cubic Hermite interpolation
  *     in t (Sec. 3.3), the change of variables phi1 = theta_i theta_j and
  *     phi2 = theta_j + (1 - theta_j) theta_i and the quadrature sums of
  *     eq. (int) (Sec. 3.4), mu(t) and E(t) (Sec. 2.1);
@@ -239,10 +241,20 @@ void or_theta_grid(int L, double gamma, double *th, double *thc) {
     }
 }
 
+/* theta-interpolation schemes of Sec. 3.3 */
+#define OR_INDEX_LAGRANGE 0 /* Lagrange on the equidistant index coordinate (default) */
+#define OR_THETA_LAGRANGE 1 /* Lagrange on theta itself */
+#define OR_INDEX_FH 2       /* Floater-Hormann rational interpolation on the index coordinate */
+#define OR_THETA_FH 3       /* Floater-Hormann on theta */
+
 typedef struct {
     int L, s;
     double gamma, D;
     const double *th, *thc, *nu;
+    int interp; /* OR_* scheme */
+    int fh_d;   /* Floater-Hormann blending degree d, 0 <= d <= s-1 */
+    int log_r;  /* interpolate log R instead of R (Appendix A) */
+    int pad;
 } or_grid;
 
 /*
@@ -260,29 +272,122 @@ static double or_xmap(const or_grid *g, double th, double thc) {
     return (double)(g->L - 1) - or_xhalf(g, thc);
 }
 double or_index_of(int L, double gamma, double th, double thc) {
-    or_grid g = {L, 10, gamma, atan(exp(gamma)) - atan(exp(-gamma)), 0, 0, 0};
+    or_grid g = {L, 10, gamma, atan(exp(gamma)) - atan(exp(-gamma)), 0, 0, 0, 0, 0, 0, 0};
     return or_xmap(&g, th, thc);
 }
 
 /*
- * s-point Lagrange interpolation on the equidistant index coordinate
- * (Sec. 3.3, "index interpolation"): nodes base..base+s-1 with
- * base = floor(x) - (s-1)/2 clamped to [0, L-s], weights
- * w_k = prod_{l != k} (x - node_l)/(node_k - node_l).
+ * A theta-coordinate to interpolate at: the grid node `node` (node >= 0, no
+ * interpolation), or the point with continuous index x, theta = th and
+ * 1 - theta = thc (both supplied, so that either is exact where it is small).
  */
-static double or_lagr(const or_grid *g, const double *row, double x) {
-    int s = g->s;
-    int base = (int)floor(x) - (s - 1) / 2;
+typedef struct {
+    int node;
+    double x, th, thc;
+} or_pt;
+
+/*
+ * The s-point stencil of a target (Sec. 3.3): nodes base..base+s-1 with
+ * base = floor(x) - (s-1)/2 clamped to [0, L-s], for every scheme.
+ */
+static int stencil_base(const or_grid *g, double x) {
+    int base = (int)floor(x) - (g->s - 1) / 2;
     if (base < 0) base = 0;
-    if (base > g->L - s) base = g->L - s;
-    double v = 0.0;
-    for (int k = 0; k < s; ++k) {
+    if (base > g->L - g->s) base = g->L - g->s;
+    return base;
+}
+
+static int on_theta(const or_grid *g) { return g->interp == OR_THETA_LAGRANGE || g->interp == OR_THETA_FH; }
+
+/*
+ * Coordinate differences of the scheme.  Index schemes: x - n and n1 - n2.
+ * Theta schemes: theta differences taken from whichever of theta and 1 - theta
+ * is exact near the points involved (theta below 1/2, the complement above), so
+ * that the clustered nodes at both ends keep their relative spacing.
+ */
+static double dq(const or_grid *g, const or_pt *q, int n) {
+    if (!on_theta(g)) return q->x - (double)n;
+    return q->th <= 0.5 ? q->th - g->th[n] : g->thc[n] - q->thc;
+}
+static double dn(const or_grid *g, int n1, int n2) {
+    if (!on_theta(g)) return (double)(n1 - n2);
+    return g->th[n1] + g->th[n2] <= 1.0 ? g->th[n1] - g->th[n2] : g->thc[n2] - g->thc[n1];
+}
+
+/* The polynomial through (node base+k, v[k]), k < n, at q: Lagrange's product form. */
+static double poly_at(const or_grid *g, const or_pt *q, int base, int n, const double *v) {
+    double val = 0.0;
+    for (int k = 0; k < n; ++k) {
         double w = 1.0;
-        for (int l = 0; l < s; ++l)
-            if (l != k) w *= (x - (double)(base + l)) / (double)(k - l);
-        v += w * row[base + k];
+        for (int l = 0; l < n; ++l)
+            if (l != k) w *= dq(g, q, base + l) / dn(g, base + k, base + l);
+        val += w * v[k];
     }
-    return v;
+    return val;
+}
+
+/*
+ * Floater-Hormann rational interpolant of degree d on the s stencil nodes
+ * (Floater and Hormann 2007, cited in Sec. 3.3), from its definition: the blend
+ * r = sum_i lam_i p_i / sum_i lam_i over the s-d windows i..i+d, p_i the
+ * polynomial through the window, lam_i = (-1)^i / prod_{j=i}^{i+d} (z - z_j).
+ * At a node r takes the node's value.
+ */
+static double fh_at(const or_grid *g, const or_pt *q, int base, const double *v) {
+    int s = g->s, d = g->fh_d;
+    for (int k = 0; k < s; ++k)
+        if (dq(g, q, base + k) == 0.0) return v[k];
+    double num = 0.0, den = 0.0;
+    for (int i = 0; i + d < s; ++i) {
+        double lam = (i & 1) ? -1.0 : 1.0;
+        for (int j = i; j <= i + d; ++j) lam /= dq(g, q, base + j);
+        num += lam * poly_at(g, q, base + i, d + 1, v + i);
+        den += lam;
+    }
+    return num / den;
+}
+
+/* The scheme's interpolant through the stencil values v[0..s-1] at q. */
+static double stencil_at(const or_grid *g, const or_pt *q, int base, const double *v) {
+    if (g->interp == OR_INDEX_FH || g->interp == OR_THETA_FH) return fh_at(g, q, base, v);
+    return poly_at(g, q, base, g->s, v);
+}
+
+/* Values of a row at the stencil of q (one value at a node); returns their count. */
+static int gather(const or_grid *g, const double *row, const or_pt *q, int *base, double *v) {
+    if (q->node >= 0) {
+        *base = q->node;
+        v[0] = row[q->node];
+        return 1;
+    }
+    *base = stencil_base(g, q->x);
+    for (int k = 0; k < g->s; ++k) v[k] = row[*base + k];
+    return g->s;
+}
+static double interp_vals(const or_grid *g, const or_pt *q, int base, int n, const double *v) {
+    return n == 1 ? v[0] : stencil_at(g, q, base, v);
+}
+static int all_positive(const double *v, int n) {
+    for (int k = 0; k < n; ++k)
+        if (!(v[k] > 0.0)) return 0;
+    return 1;
+}
+
+#define OR_MAX_S 16
+
+/*
+ * A row interpolated at q.  With as_log (the R field under the log option of
+ * Appendix A) the interpolant of log R is exponentiated, unless a stencil value
+ * is not positive: then R itself is interpolated.
+ */
+static double row_at(const or_grid *g, const double *row, const or_pt *q, int as_log) {
+    double v[OR_MAX_S];
+    int base, n = gather(g, row, q, &base, v);
+    if (as_log && all_positive(v, n)) {
+        for (int k = 0; k < n; ++k) v[k] = log(v[k]);
+        return exp(interp_vals(g, q, base, n, v));
+    }
+    return interp_vals(g, q, base, n, v);
 }
 
 /* Stored history in the oracle's own layout: four [M][L] arrays. */
@@ -295,56 +400,82 @@ typedef struct {
     const double *yC, *yR;      /* current stage slice C(t, theta_i t), R(t, theta_i t) */
 } or_hist;
 
-/* value of a [M][L] history array at slice n, at node i (x < 0) or index x */
-static double slice_at(const or_grid *g, const double *arr, int n, int node, double x) {
-    const double *row = arr + (size_t)n * g->L;
-    return node >= 0 ? row[node] : or_lagr(g, row, x);
-}
-
 /*
- * (C, R)(tau, theta-coordinate) for 0 <= tau <= t, the theta-coordinate being
- * the grid node `node` (node >= 0) or the continuous index x.
+ * (C, R)(tau, q) for 0 <= tau <= t: a rule in t over at most two slices, each
+ * slice theta-interpolated at q first (Sec. 3.3, the 2-D stencil of I_2).
  *  - tau inside the stored slices with known d/dt: cubic Hermite in t between
- *    the bracketing slices, theta-interpolating value and d/dt on each
- *    (Sec. 3.3, the 2-D stencil for I_2);
- *  - tau above the last slice with known d/dt (inside the current step): the
- *    quadratic in t through value and d/dt at that slice and the value of the
- *    current stage slice at t.
+ *    the bracketing slices m, m+1 from value and d/dt on each;
+ *  - tau above the last slice b with known d/dt (inside the current step): the
+ *    quadratic in t through value and d/dt at b and the value of the current
+ *    stage slice at t;
+ *  - only t_0 stored: slice 0 (or the stage slice before any slice has d/dt).
+ * Under the log option, R follows the same rule applied to log R with the
+ * scaled derivative (dR/dt)/R, whenever every R value the rule reads is
+ * positive; otherwise R itself.
  */
-static void or_hist_at(const or_grid *g, const or_hist *H, double tau, int node, double x, double out[2]) {
-    const double *cur[2] = {H->yC, H->yR};
-    if (H->nb == 0) { /* only t = t_0 exists */
-        for (int f = 0; f < 2; ++f) out[f] = node >= 0 ? cur[f][node] : or_lagr(g, cur[f], x);
-        return;
+static void or_hist_at(const or_grid *g, const or_hist *H, double tau, const or_pt *q, double out[2]) {
+    int L = g->L;
+    /* slice a (and b when nb_used == 2); -1 stands for the stage slice; weights on
+     * value and d/dt of each */
+    int sa = -1, sb = -1, two = 0;
+    double wa = 1.0, wda = 0.0, wb = 0.0, wdb = 0.0;
+    if (H->nb >= 1) {
+        int b = H->nb - 1;
+        double tb = H->t[b];
+        if (tau <= tb) {
+            if (b == 0) {
+                sa = 0;
+            } else {
+                int m = 0;
+                while (m + 1 < b && H->t[m + 1] <= tau) ++m;
+                double h = H->t[m + 1] - H->t[m];
+                double u = (tau - H->t[m]) / h;
+                sa = m;
+                sb = m + 1;
+                two = 1;
+                wa = 2 * u * u * u - 3 * u * u + 1;
+                wda = (u * u * u - 2 * u * u + u) * h;
+                wb = -2 * u * u * u + 3 * u * u;
+                wdb = (u * u * u - u * u) * h;
+            }
+        } else {
+            double h = H->tcur - tb;
+            double u = (tau - tb) / h;
+            sa = b;
+            sb = -1;
+            two = 1;
+            wa = 1.0 - u * u;
+            wda = h * (u - u * u);
+            wb = u * u;
+        }
     }
-    const double *val[2] = {H->C, H->R};
-    const double *der[2] = {H->dC, H->dR};
-    int b = H->nb - 1;
-    double tb = H->t[b];
-    if (tau <= tb) {
-        if (b == 0) {
-            for (int f = 0; f < 2; ++f) out[f] = slice_at(g, val[f], 0, node, x);
-            return;
+    const double *val[2] = {H->C, H->R}, *der[2] = {H->dC, H->dR}, *cur[2] = {H->yC, H->yR};
+    for (int f = 0; f < 2; ++f) {
+        const double *va = sa < 0 ? cur[f] : val[f] + (size_t)sa * L;
+        const double *da = sa < 0 ? NULL : der[f] + (size_t)sa * L;
+        const double *vb = sb < 0 ? cur[f] : val[f] + (size_t)sb * L;
+        const double *db = sb < 0 ? NULL : der[f] + (size_t)sb * L;
+        double Va[OR_MAX_S], Da[OR_MAX_S], Vb[OR_MAX_S], Db[OR_MAX_S];
+        int base, n = gather(g, va, q, &base, Va);
+        if (da) gather(g, da, q, &base, Da);
+        if (two) gather(g, vb, q, &base, Vb);
+        if (two && db) gather(g, db, q, &base, Db);
+        int use_log = f == 1 && g->log_r && all_positive(Va, n) && (!two || all_positive(Vb, n));
+        if (use_log) {
+            for (int k = 0; k < n; ++k) {
+                if (da) Da[k] = Da[k] / Va[k];
+                Va[k] = log(Va[k]);
+                if (two) {
+                    if (db) Db[k] = Db[k] / Vb[k];
+                    Vb[k] = log(Vb[k]);
+                }
+            }
         }
-        int m = 0;
-        while (m + 1 < b && H->t[m + 1] <= tau) ++m;
-        double h = H->t[m + 1] - H->t[m];
-        double u = (tau - H->t[m]) / h;
-        double h00 = 2 * u * u * u - 3 * u * u + 1, h10 = u * u * u - 2 * u * u + u;
-        double h01 = -2 * u * u * u + 3 * u * u, h11 = u * u * u - u * u;
-        for (int f = 0; f < 2; ++f) {
-            double y0 = slice_at(g, val[f], m, node, x), d0 = slice_at(g, der[f], m, node, x);
-            double y1 = slice_at(g, val[f], m + 1, node, x), d1 = slice_at(g, der[f], m + 1, node, x);
-            out[f] = h00 * y0 + h10 * h * d0 + h01 * y1 + h11 * h * d1;
-        }
-    } else {
-        double h = H->tcur - tb;
-        double u = (tau - tb) / h;
-        for (int f = 0; f < 2; ++f) {
-            double yb = slice_at(g, val[f], b, node, x), db = slice_at(g, der[f], b, node, x);
-            double yc = node >= 0 ? cur[f][node] : or_lagr(g, cur[f], x);
-            out[f] = yb * (1.0 - u * u) + db * h * (u - u * u) + yc * u * u;
-        }
+        double r = wa * interp_vals(g, q, base, n, Va);
+        if (da) r += wda * interp_vals(g, q, base, n, Da);
+        if (two) r += wb * interp_vals(g, q, base, n, Vb);
+        if (two && db) r += wdb * interp_vals(g, q, base, n, Db);
+        out[f] = use_log ? exp(r) : r;
     }
 }
 
@@ -392,18 +523,20 @@ int or_theta_rhs(const or_model *m, const or_grid *g, const or_hist *H, double m
         double S[9] = {0};
         for (int i = 0; i < L; ++i) {
             double thi = g->th[i], thci = g->thc[i], w = g->nu[i];
-            double xa = or_xmap(g, thi * thj, thci + thi * thcj);
-            double aC = or_lagr(g, H->yC, xa), aR = or_lagr(g, H->yR, xa);
+            double tha = thi * thj, thca = thci + thi * thcj;
+            or_pt qa = {-1, or_xmap(g, tha, thca), tha, thca};
+            double aC = row_at(g, H->yC, &qa, 0), aR = row_at(g, H->yR, &qa, g->log_r);
             double phi = thj + thcj * thi, phic = thcj * thci;
-            double xb = or_xmap(g, phi, phic);
-            double bC = or_lagr(g, H->yC, xb), bR = or_lagr(g, H->yR, xb);
+            or_pt qb = {-1, or_xmap(g, phi, phic), phi, phic};
+            double bC = row_at(g, H->yC, &qb, 0), bR = row_at(g, H->yR, &qb, g->log_r);
             double cv[2];
-            or_hist_at(g, H, tp, i, 0.0, cv);
+            or_pt qc = {i, 0.0, thi, thci};
+            or_hist_at(g, H, tp, &qc, cv);
             double psi = 0.0, psic = 1.0; /* psi = 0/0 := 0 at i = j = 0 */
             if (phi > 0.0) { psi = thj / phi; psic = thcj * thi / phi; }
-            double xd = or_xmap(g, psi, psic);
+            or_pt qd = {-1, or_xmap(g, psi, psic), psi, psic};
             double dv[2];
-            or_hist_at(g, H, phi * t, -1, xd, dv);
+            or_hist_at(g, H, phi * t, &qd, dv);
             double cC = cv[0], cR = cv[1], dC = dv[0], dR = dv[1];
             S[0] += w * or_f2(m, aC) * aR * cC;
             S[1] += w * or_f1(m, aC) * cR;
@@ -416,7 +549,8 @@ int or_theta_rhs(const or_model *m, const or_grid *g, const or_hist *H, double m
             S[8] += w * (or_f2(m, cC) * cR * cC + or_f1(m, cC) * cR);
         }
         double c0[2];
-        or_hist_at(g, H, tp, 0, 0.0, c0); /* C(t', 0) */
+        or_pt q0 = {0, 0.0, 0.0, 1.0};
+        or_hist_at(g, H, tp, &q0, c0); /* C(t', 0) */
         double Ct0 = H->yC[0];            /* C(t, 0) */
         double Cj = H->yC[j], Rj = H->yR[j];
         double d1C = -mu * Cj + t * (thj * S[0] + thj * S[1] + thcj * S[2]) + m->beta0 * or_f1(m, Ct0) * c0[0];
@@ -433,9 +567,12 @@ int or_theta_rhs(const or_model *m, const or_grid *g, const or_hist *H, double m
     return 0;
 }
 
-/* Interpolated history value (C, R) at (tau, index x) -- exported for tests. */
-void or_hist_value(const or_grid *g, const or_hist *H, double tau, int node, double x, double *out2) {
-    or_hist_at(g, H, tau, node, x, out2);
+/* Interpolated history value (C, R) at tau and the node, or at the point with
+ * index x and theta th, 1 - theta = thc -- exported for tests. */
+void or_hist_value(const or_grid *g, const or_hist *H, double tau, int node, double x, double th, double thc,
+                   double *out2) {
+    or_pt q = {node, x, th, thc};
+    or_hist_at(g, H, tau, &q, out2);
 }
 
 /* ======================================================================

@@ -251,6 +251,82 @@ def kernel_bench(pk, args) -> dict:
             "achieved_GBps": alg / (avg_us * 1e-6) / 1e9, "calibration_copies": cal}
 
 
+STENCILS = [  # (name, theta_interp, s, fh_d, log_r)
+    ("index-lagrange s=10 (default)", 0, 10, 0, False),
+    ("theta-lagrange s=10", 1, 10, 0, False),
+    ("index-fh s=10 d=5", 2, 10, 5, False),
+    ("theta-fh s=10 d=5", 3, 10, 5, False),
+    ("theta-fh s=14 d=9", 3, 14, 9, False),
+    ("index-lagrange s=10 log-R", 0, 10, 0, True),
+]
+
+
+def stencil_sweep(pk, torch, args) -> dict:
+    """Cost against accuracy of the theta-stencils (Sec. 3.3) and the log-R option.
+    Cost: the history-integral kernel's average launch at the L = 4096 steady
+    state (M = 2500 slices to t = 200, stage at t = 200.08; HIP events).
+    Accuracy: the largest error of one right-hand side along fixed theta against
+    the exact p = 2 solution at T = 0 (history and stage from its closed form, 800
+    slices to t = 8, L = 96 and 192)."""
+    import numpy as np
+
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import inputs
+    import p2_exact as px
+
+    rows = []
+    for name, interp, s_, d, lr in STENCILS:
+        L, M, t_last, t = 4096, 2500, 200.0, 200.08
+        params = pk.make_params({3: 0.5, 4: 0.5}, 0.55, t_max=1e7, L=L, M_cap=M, eps=1e-8, s=s_,
+                                theta_interp=interp, fh_d=d, log_r=lr)
+        sv = pk.Solver(params)
+        th = sv.read(pk.F_THETA)
+        times = inputs.geometric_times(M, t_last, t_first=0.01)
+        C, R, dC, dR = inputs.smooth_history(th, times, 1)
+        sv.set_history(times, C, R, dC, dR)
+        del C, R, dC, dR
+        yC, yR = inputs.smooth_stage(th, t, 1)
+        yC, yR = torch.tensor(yC, device="cuda"), torch.tensor(yR, device="cuda")
+        for _ in range(3):
+            sv.rhs(t, yC, yR, M)
+        sv.timing(True)
+        for _ in range(10):
+            sv.rhs(t, yC, yR, M)
+        torch.cuda.synchronize()
+        n, ms, _ = sv.timing_read(pk.K_HIST_INTEGRAL)
+        sv.close()
+        errs = []
+        for Lp in (96, 192):
+            tp = 8.0
+            sp = pk.Solver(pk.make_params({2: 1.0}, 0.0, t_max=1e3, L=Lp, M_cap=820, s=s_, theta_interp=interp,
+                                          fh_d=d, log_r=lr))
+            thp = sp.read(pk.F_THETA)
+            tt = np.concatenate([[0.0], np.geomspace(1e-3, tp - 0.0125, 799)])
+            Cp = np.array([px.C0(x, thp * x) for x in tt])
+            Rp = np.array([px.R0(x, thp * x) for x in tt])
+            dCp = np.array([sum(a * w for a, w in zip(px.dC0(x, thp * x), (1, thp))) for x in tt])
+            dRp = np.array([sum(a * w for a, w in zip(px.dR0(x, thp * x), (1, thp))) for x in tt])
+            Cp[:, -1] = Rp[:, -1] = 1.0
+            sp.set_history(tt, Cp, Rp, dCp, dRp)
+            ysC, ysR = px.C0(tp, thp * tp), px.R0(tp, thp * tp)
+            ysC[-1] = ysR[-1] = 1.0
+            gC, gR, _, _ = sp.rhs(tp, torch.tensor(ysC, device="cuda"), torch.tensor(ysR, device="cuda"), tt.size)
+            sp.close()
+            a, b = px.dC0(tp, thp * tp)
+            exC = a + thp * b
+            a, b = px.dR0(tp, thp * tp)
+            exR = a + thp * b
+            errs.append(float(max(np.abs(gC.cpu().numpy() - exC)[:-1].max(), np.abs(gR.cpu().numpy() - exR)[:-1].max())))
+        rows.append({"scheme": name, "hist_integral_avg_launch_us": ms / n * 1e3, "p2_rhs_max_error_L96": errs[0],
+                     "p2_rhs_max_error_L192": errs[1]})
+        log(f"stencil {name}: {ms / n * 1e3:.1f} us per launch; p=2 RHS error {errs[0]:.2e} (L=96), "
+            f"{errs[1]:.2e} (L=192)")
+    base = rows[0]["hist_integral_avg_launch_us"]
+    for r in rows:
+        r["cost_vs_default"] = r["hist_integral_avg_launch_us"] / base
+    return {"stencils": rows}
+
+
 def uniform_c1(pk, torch, with_oracle: bool) -> dict:
     """The uniform-grid baseline: pure p=3 (f = q^3/2), T = 0.5, h = 0.05, N = 1000
     (t_max = 50), classical RK4 with trapezoid history integrals.  Time to
@@ -347,6 +423,8 @@ def main() -> int:
     ap.add_argument("--serving", type=int, default=24, help="requests in the serving sweep (0: skip)")
     ap.add_argument("--kernel", action="store_true",
                     help="time the history-integral kernel alone on a synthetic full-size history")
+    ap.add_argument("--stencils", action="store_true",
+                    help="only the cost and accuracy of the theta-stencil schemes and the log-R option")
     ap.add_argument("--kernel-slices", type=int, default=2500,
                     help="history slices of --kernel (the solver's steady state holds about 2500)")
     args = ap.parse_args()
@@ -363,6 +441,9 @@ def main() -> int:
     torch.cuda.set_device(0)
     if args.kernel:
         print(json.dumps(kernel_bench(pk, args)), flush=True)
+        return 0
+    if args.stencils:
+        print(json.dumps(stencil_sweep(pk, torch, args)), flush=True)
         return 0
     prec_name = args.precision
     other = "fp32c" if prec_name == "fp64" else "fp64"

@@ -60,6 +60,13 @@ enum { DMFE_UNIFORM = 0, DMFE_ADAPTIVE = 1 };
 enum { DMFE_FP64 = 0, DMFE_FP32_COMP = 1 };
 enum { DMFE_SCHEME_DP5 = 0, DMFE_SCHEME_SSPRK104 = 1 };
 enum { DMFE_MAX_TERMS = 8, DMFE_MAX_P = 16 };
+/* theta-interpolation schemes (Sec. 3.3) */
+enum {
+    DMFE_INTERP_INDEX_LAGRANGE = 0, /* Lagrange on the equidistant index coordinate (default) */
+    DMFE_INTERP_THETA_LAGRANGE = 1, /* Lagrange on theta itself */
+    DMFE_INTERP_INDEX_FH = 2,       /* Floater-Hormann rational interpolation on the index coordinate */
+    DMFE_INTERP_THETA_FH = 3        /* Floater-Hormann on theta */
+};
 
 /*
  * Problem statement (Sec. 2.1, 3.2, 3.5, Appendix B).
@@ -81,11 +88,25 @@ enum { DMFE_MAX_TERMS = 8, DMFE_MAX_P = 16 };
  *   eps                 tolerance on the 1-norm RK error (Sec. 3.5); sparsification drops
  *                       a slice whose residual is below eps/10 (Sec. 3.6)
  *   dt0, dt_min         first step and smallest allowed step
- *   s                   theta stencil size (4 <= s <= 12; 0 means 10)
+ *   s                   theta stencil size (even, 4 <= s <= 16; 0 means 10)
  *   auto_passes         sparsification passes run when M reaches M_cap (0 means 1)
  *   grid_alpha, grid_delta  flattening parameters of eq. (theta); only alpha = 0 is supported
  *   scheme_policy       0: DP5 until its stability boundary, then SSPRK(10,4) (default);
  *                       1: SSPRK(10,4) from the start; 2: DP5 only
+ *   theta_interp        DMFE_INTERP_*: how a value between theta-grid nodes is formed from
+ *                       the s stencil nodes around it (Sec. 3.3).  The stencil is the
+ *                       same for every scheme: nodes base..base+s-1, base = floor(x) -
+ *                       (s-1)/2 clamped to [0, L-s], x the continuous index of the target.
+ *                       Theta schemes difference theta below 1/2 and 1 - theta above.
+ *   fh_d                Floater-Hormann blending degree d (0 <= d <= s-1; read by the FH
+ *                       schemes only): rational, no real poles, exact on polynomials of
+ *                       degree d; d = s-1 is the polynomial interpolant
+ *   log_r               1: interpolate log R and the scaled derivative (dR/dt)/R with the
+ *                       same rules in theta and in t and exponentiate; a target any of whose
+ *                       stencil values of R is <= 0 interpolates R itself (Appendix A).
+ *                       The sparsification residual stays the integral of R's Hermite
+ *                       interpolant.
+ * The serving pool admits the default stencil only (s = 10, index Lagrange, log_r = 0).
  */
 typedef struct dmfe_params {
     int32_t n_terms;
@@ -108,7 +129,9 @@ typedef struct dmfe_params {
     double grid_alpha;
     double grid_delta;
     int32_t scheme_policy;
-    int32_t reserved0;
+    int32_t theta_interp;
+    int32_t fh_d;
+    int32_t log_r;
 } dmfe_params;
 
 /*
@@ -305,7 +328,8 @@ typedef struct dmfe_pool_times {
  * arena; res->stream orders all work of the pool. */
 dmfe_status dmfe_pool_create(const dmfe_pool_params *pp, const dmfe_resources *res, dmfe_pool **out);
 /* Queue a solve (adaptive mode); *request_id identifies it.  DMFE_ERR_NOMEM if it
- * can never fit, DMFE_ERR_UNSUPPORTED for s != 10 or a precision other than the pool's. */
+ * can never fit, DMFE_ERR_UNSUPPORTED for a stencil other than the default (s != 10, theta_interp
+ * != DMFE_INTERP_INDEX_LAGRANGE or log_r != 0) or a precision other than the pool's. */
 dmfe_status dmfe_pool_submit(dmfe_pool *pool, const dmfe_params *params, uint64_t *request_id);
 /* Run up to max_ticks stage ticks (returns early when nothing is running and
  * nothing can be admitted); stats may be NULL. */

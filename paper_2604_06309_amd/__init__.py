@@ -28,6 +28,8 @@ ERR_INVALID, ERR_NOMEM, ERR_CAPACITY, ERR_STEP_UNDERFLOW = -1, -2, -3, -4
 ERR_NONFINITE, ERR_DEVICE, ERR_UNSUPPORTED, ERR_BUFFER = -5, -6, -7, -8
 UNIFORM, ADAPTIVE = 0, 1
 FP64, FP32_COMP = 0, 1
+# theta-interpolation schemes (DMFE_INTERP_*)
+INTERP_INDEX_LAGRANGE, INTERP_THETA_LAGRANGE, INTERP_INDEX_FH, INTERP_THETA_FH = 0, 1, 2, 3
 SCHEME_DP5, SCHEME_SSPRK104 = 0, 1
 F_T_GRID, F_THETA, F_THETA_C, F_NU, F_C, F_R, F_DC, F_DR, F_ENERGY, F_MU = range(10)
 K_HIST_INTEGRAL, K_STAGE_PREP, K_RK, K_SPARSIFY = range(4)
@@ -40,7 +42,8 @@ class dmfe_params(ctypes.Structure):
                 ("h", ctypes.c_double), ("N", ctypes.c_int64), ("L", ctypes.c_int32), ("M_cap", ctypes.c_int32),
                 ("eps", ctypes.c_double), ("dt0", ctypes.c_double), ("dt_min", ctypes.c_double),
                 ("s", ctypes.c_int32), ("auto_passes", ctypes.c_int32), ("grid_alpha", ctypes.c_double),
-                ("grid_delta", ctypes.c_double), ("scheme_policy", ctypes.c_int32), ("reserved0", ctypes.c_int32)]
+                ("grid_delta", ctypes.c_double), ("scheme_policy", ctypes.c_int32), ("theta_interp", ctypes.c_int32),
+                ("fh_d", ctypes.c_int32), ("log_r", ctypes.c_int32)]
 
 
 class dmfe_resources(ctypes.Structure):
@@ -153,8 +156,10 @@ def _ptr(a: np.ndarray):
 def make_params(terms: dict, T: float, *, beta0: float = 0.0, t_max: float = 1e4, mode: int = ADAPTIVE,
                 precision: int = FP64, h: float = 0.05, N: int = 1000, L: int = 512, M_cap: int = 0,
                 eps: float = 1e-8, dt0: float = 1e-4, dt_min: float = 1e-12, s: int = 10, auto_passes: int = 1,
-                scheme_policy: int = 0, grid_alpha: float = 0.0, grid_delta: float = 0.0) -> dmfe_params:
-    """terms maps p -> a_p^2 (f(q) = sum_p a_p^2 q^p / 2, Sec. 2.1)."""
+                scheme_policy: int = 0, grid_alpha: float = 0.0, grid_delta: float = 0.0,
+                theta_interp: int = INTERP_INDEX_LAGRANGE, fh_d: int = 3, log_r: bool = False) -> dmfe_params:
+    """terms maps p -> a_p^2 (f(q) = sum_p a_p^2 q^p / 2, Sec. 2.1).  theta_interp,
+    fh_d and log_r choose the theta-stencil (Sec. 3.3) and the log-R option."""
     p = dmfe_params()
     p.n_terms = len(terms)
     for k, (pp, a2) in enumerate(sorted(terms.items())):
@@ -165,6 +170,7 @@ def make_params(terms: dict, T: float, *, beta0: float = 0.0, t_max: float = 1e4
     p.L, p.M_cap, p.eps, p.dt0, p.dt_min = int(L), int(M_cap), float(eps), float(dt0), float(dt_min)
     p.s, p.auto_passes, p.scheme_policy = int(s), int(auto_passes), int(scheme_policy)
     p.grid_alpha, p.grid_delta = float(grid_alpha), float(grid_delta)
+    p.theta_interp, p.fh_d, p.log_r = int(theta_interp), int(fh_d), int(bool(log_r))
     return p
 
 

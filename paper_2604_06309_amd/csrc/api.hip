@@ -132,6 +132,8 @@ Layout make_layout(const dmfe_params& p) {
         lo.th = take(L * sizeof(double));
         lo.thc = take(L * sizeof(double));
         lo.nu = take(L * sizeof(double));
+        const size_t s = size_t(p.s == 0 ? 10 : p.s);
+        lo.bw = take(p.theta_interp != DMFE_INTERP_INDEX_LAGRANGE ? (L - s + 1) * (s + 1) * sizeof(double) : 0);
         lo.X = take(L * L * sizeof(double));
         lo.Xd = take(L * L * sizeof(double));
         lo.y = take(L * sizeof(YPoint));
@@ -176,7 +178,11 @@ dmfe_status validate(const dmfe_params* p) {
     }
     if (p->mode != DMFE_ADAPTIVE) return DMFE_ERR_INVALID;
     const int s = p->s == 0 ? 10 : p->s;
-    if (s < 4 || s > 12 || (s & 1)) return DMFE_ERR_INVALID;
+    if (s < 4 || s > 16 || (s & 1)) return DMFE_ERR_INVALID;
+    if (p->theta_interp < DMFE_INTERP_INDEX_LAGRANGE || p->theta_interp > DMFE_INTERP_THETA_FH) return DMFE_ERR_INVALID;
+    const bool fh = p->theta_interp == DMFE_INTERP_INDEX_FH || p->theta_interp == DMFE_INTERP_THETA_FH;
+    if (fh && (p->fh_d < 0 || p->fh_d > s - 1)) return DMFE_ERR_INVALID;
+    if (p->log_r != 0 && p->log_r != 1) return DMFE_ERR_INVALID;
     if (p->L < std::max(2 * s, 16) || p->L > 16384) return DMFE_ERR_INVALID;
     const int Mc = p->M_cap == 0 ? p->L : p->M_cap;
     if (Mc < 16 || Mc > 16384) return DMFE_ERR_INVALID;
@@ -278,6 +284,10 @@ StageArgs stage_args(const dmfe_handle* h, double t, int nb, const YPoint* y, YP
     a.kout = kout;
     a.store = store;
     a.diag = h->at<double>(h->lo.diag);
+    a.interp = h->p.theta_interp;
+    a.log_r = h->p.log_r;
+    a.bw = h->at<double>(h->lo.bw);
+    for (int k = 0; k < 16; ++k) a.fh_c[k] = h->fh_c[k];
     a.m = h->m;
     return a;
 }
@@ -749,6 +759,16 @@ dmfe_status dmfe_create(const dmfe_params* params, const dmfe_resources* res, dm
         (e = hipMemcpyAsync(h->at<double>(h->lo.nu), h->nu.data(), sizeof(double) * L, hipMemcpyHostToDevice,
                             h->stream)))
         return bail(fail(e, "hipMemcpyAsync"));
+    if (h->p.theta_interp != DMFE_INTERP_INDEX_LAGRANGE) {
+        std::vector<double> bw(size_t(L - h->s + 1) * (h->s + 1));
+        stencil_coefficients(L, h->s, h->p.theta_interp, h->p.fh_d, h->th.data(), h->thc.data(), bw.data());
+        for (int k = 0; k < h->s; ++k) h->fh_c[k] = bw[k];
+        // synchronous: the host table goes out of scope below
+        if ((e = hipMemcpyAsync(h->at<double>(h->lo.bw), bw.data(), sizeof(double) * bw.size(),
+                                hipMemcpyHostToDevice, h->stream)) != hipSuccess ||
+            (e = hipStreamSynchronize(h->stream)) != hipSuccess)
+            return bail(fail(e, "hipMemcpyAsync"));
+    }
     {
         GridArgs g{};
         g.L = L;

@@ -15,6 +15,8 @@ namespace dmfe {
 double lambert_gamma(double tmax);
 void theta_grid(int L, double gamma, double* th, double* thc);
 int quintic_weights(int L, const double* th, double* nu);
+// rows b = 0..L-s of s barycentric coefficients and the inverse stencil span
+void stencil_coefficients(int L, int s, int scheme, int d, const double* th, const double* thc, double* out);
 
 // ---------------------------------------------------------------- model on the device
 // f(q) = sum_k fc[k] q^k, f'(q) = sum_k f1[k] q^k, f''(q) = sum_k f2[k] q^k with
@@ -63,6 +65,10 @@ struct StageArgs {
     int fp32;            // history precision: 0 = HPoint, 1 = HPoint32
     double* diag;        // computed values of row L-1 [2]
     Model m;
+    int interp;          // DMFE_INTERP_* scheme in theta
+    int log_r;           // interpolate log R (falls back to R on non-positive stencils)
+    const double* bw;    // barycentric stencil coefficients [L-s+1][s+1] (schemes other than index Lagrange)
+    double fh_c[16];     // index Floater-Hormann: the coefficients, the same for every stencil base
 };
 
 // Run-constant data of the theta grid used by the coordinate precompute.

@@ -2,8 +2,10 @@
 //   gamma = -W_{-1}(-1/t_max)           (eq. theta)
 //   theta_i, 1 - theta_i                (eq. theta at alpha = 0)
 //   nu_i                                (Sec. 3.4: integral of the global quintic spline)
+//   barycentric stencil coefficients    (Sec. 3.3: the alternative theta-stencils)
 #include "dmfe_internal.h"
 
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -121,6 +123,50 @@ int quintic_weights(int L, const double* th, double* nu) {
         nu[k] = acc / at(k, k);
     }
     return 0;
+}
+
+// Coefficients of the barycentric form of the theta-stencils (Sec. 3.3), one
+// row per stencil base b = 0..L-s: c_0..c_{s-1} and, last, the inverse of the
+// stencil's coordinate span (1 on the index coordinate).  A target z is given
+// the weights w_k = c_k P_k / sum_m c_m P_m with P_k = prod_{m != k} dz_m and
+// dz_m = (z - z_m) * inverse span, for
+//   Lagrange:          c_k = 1 / prod_{m != k} (z_k - z_m)
+//   Floater-Hormann d: c_k = sum over the windows i..i+d holding k (0 <= i <= s-1-d)
+//                      of (-1)^i prod_{j = i..i+d, j != k} 1 / (z_k - z_j)
+// (Floater and Hormann 2007).  Node differences are scaled by the inverse span
+// and each row by its largest |c_k|; the form is invariant under both.  On
+// theta, differences are taken from theta where both nodes sum to at most 1 and
+// from 1 - theta otherwise, which keeps the clustered end nodes apart.
+void stencil_coefficients(int L, int s, int scheme, int d, const double* th, const double* thc, double* out) {
+    const bool on_theta = scheme == DMFE_INTERP_THETA_LAGRANGE || scheme == DMFE_INTERP_THETA_FH;
+    const bool fh = scheme == DMFE_INTERP_INDEX_FH || scheme == DMFE_INTERP_THETA_FH;
+    if (!fh) d = s - 1;  // one window: the Lagrange weights
+    std::vector<double> z(s);
+    for (int b = 0; b + s <= L; ++b) {
+        auto diff = [&](int k, int m) {  // z_k - z_m, scaled below
+            if (!on_theta) return double(k - m);
+            const int n1 = b + k, n2 = b + m;
+            return th[n1] + th[n2] <= 1.0 ? th[n1] - th[n2] : thc[n2] - thc[n1];
+        };
+        const double span = diff(s - 1, 0);
+        const double inv = 1.0 / span;
+        double* row = out + size_t(b) * (s + 1);
+        double big = 0.0;
+        for (int k = 0; k < s; ++k) {
+            double c = 0.0;
+            const int i_lo = std::max(0, k - d), i_hi = std::min(k, s - 1 - d);
+            for (int i = i_lo; i <= i_hi; ++i) {
+                double prod = (i & 1) ? -1.0 : 1.0;
+                for (int j = i; j <= i + d; ++j)
+                    if (j != k) prod /= diff(k, j) * inv;
+                c += prod;
+            }
+            row[k] = c;
+            big = std::max(big, std::fabs(c));
+        }
+        for (int k = 0; k < s; ++k) row[k] /= big;
+        row[s] = on_theta ? inv : 1.0;
+    }
 }
 
 }  // namespace dmfe

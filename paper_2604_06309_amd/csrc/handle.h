@@ -21,7 +21,7 @@ struct Tableau {
 };
 
 struct Layout {
-    size_t hist, thist, slot, th, thc, nu, X, Xd, y, ys, ynew, k, mue, eps, diag, eps_n, obs, rhs_y, rhs_k, io, total;
+    size_t hist, thist, slot, th, thc, nu, bw, X, Xd, y, ys, ynew, k, mue, eps, diag, eps_n, obs, rhs_y, rhs_k, io, total;
     // uniform
     size_t uC, uR, uE, uy0, uy1, uys, uk;
 };
@@ -49,6 +49,7 @@ struct dmfe_handle {
     int fp32 = 0;  // history stored as HPoint32
     double gamma = 0, Dg = 0, xscale = 0, eg = 0, egi = 0;
     std::vector<double> th, thc, nu;
+    double fh_c[16] = {};  // index Floater-Hormann coefficients (every stencil base alike)
     std::vector<double> thist;  // logical order
     std::vector<int> slot;      // logical order
     std::vector<int> free_slots;

@@ -153,6 +153,114 @@ __device__ __forceinline__ void interp4(const HP* row, int base, const R (&w)[S]
     }
 }
 
+// ---------------------------------------------------------------- the other theta schemes
+// Weights of the stencil of a target under the handle's scheme (Sec. 3.3); the
+// target has continuous index x, theta tq and 1 - theta tqc.  Index Lagrange is
+// the closed form above; the others use the barycentric form
+//   w_k = c_k P_k / sum_m c_m P_m,  P_k = prod_{m != k} dz_m,
+// with dz_m = u - m on the index coordinate (u = x - base) and the scaled theta
+// differences (tq - theta_m) or ((1 - theta_m) - tqc) (tq above 1/2) on theta,
+// and the coefficients c_k of the stencil's base from the host table.  At a node
+// every P_k but one vanishes, so the weights are exact unit vectors there.
+//
+// Kernel variants: the default stencil (index Lagrange, R itself) and three for
+// the other options, each compiled on its own so that no variant carries the
+// registers of another.
+enum : int { kVarDefault = 0, kVarIndexLagrangeLog = 1, kVarIndexFH = 2, kVarTheta = 3, kVarIndexFHLog = 4,
+              kVarThetaLog = 5 };
+constexpr bool var_log(int v) { return v == kVarIndexLagrangeLog || v == kVarIndexFHLog || v == kVarThetaLog; }
+constexpr bool var_index_fh(int v) { return v == kVarIndexFH || v == kVarIndexFHLog; }
+constexpr bool var_theta(int v) { return v == kVarTheta || v == kVarThetaLog; }
+template <int S, int VAR>
+__device__ __forceinline__ int stencil_weights(const StageArgs& a, double x, double tq, double tqc, double (&w)[S]) {
+    if constexpr (VAR == kVarDefault || VAR == kVarIndexLagrangeLog) return lagrange<S>(x, a.L, w);
+    int base = int(floor(x)) - (S - 1) / 2;
+    base = base < 0 ? 0 : (base > a.L - S ? a.L - S : base);
+    // on the index coordinate every stencil has the same coefficients (kernel arguments)
+    const double* c = var_index_fh(VAR) ? a.fh_c : a.bw + size_t(base) * (S + 1);
+    double dz[S];
+    if constexpr (var_index_fh(VAR)) {
+        const double u = x - double(base);
+#pragma unroll
+        for (int k = 0; k < S; ++k) dz[k] = u - double(k);
+    } else {
+        // theta below 1/2, the complement above: dz = +-(z - z_k) / span
+        const bool lo = tq <= 0.5;
+        const double* zn = lo ? a.th : a.thc;
+        const double zt = lo ? tq : tqc;
+        const double f = lo ? c[S] : -c[S];
+#pragma unroll
+        for (int k = 0; k < S; ++k) dz[k] = (zt - zn[base + k]) * f;
+    }
+    double pre[S];
+    double acc = 1.0;
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+        pre[k] = acc;
+        acc *= dz[k];
+    }
+    acc = 1.0;
+    double sum = 0.0;
+#pragma unroll
+    for (int k = S - 1; k >= 0; --k) {
+        w[k] = c[k] * pre[k] * acc;
+        acc *= dz[k];
+        sum += w[k];
+    }
+    const double inv = 1.0 / sum;
+#pragma unroll
+    for (int k = 0; k < S; ++k) w[k] *= inv;
+    return base;
+}
+
+// The log-R option (Appendix A): log R is interpolated with the same weights and
+// exponentiated; a target with a stencil value R <= 0 keeps the plain value.
+template <int S>
+__device__ __forceinline__ double log_interp_y(const YPoint* row, int base, const double (&w)[S], double plain) {
+    double l = 0.0;
+    bool pos = true;
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+        const double r = row[base + k].r;
+        pos = pos && r > 0.0;
+        l = fma(w[k], log(r), l);  // not used when some r <= 0
+    }
+    return pos ? exp(l) : plain;
+}
+// One slot of the history under the log option: the theta-interpolated log R
+// and scaled derivative (dR/dt)/R.  The stage slot carries no derivative: its
+// two R fields hold the value (FP64: R and 0; FP32: R and its remainder).
+template <int S, class HP>
+__device__ __forceinline__ bool log_interp_slot(const HP* row, int base, const double (&w)[S], bool stage,
+                                                double& lv, double& ld) {
+    lv = 0.0;
+    ld = 0.0;
+    bool pos = true;
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+        const HP v = row[base + k];
+        const double r = stage ? double(v.r) + double(v.dr) : double(v.r);
+        pos = pos && r > 0.0;
+        lv = fma(w[k], log(r), lv);
+        if (!stage) ld = fma(w[k], double(v.dr) / r, ld);
+    }
+    return pos;
+}
+// R at a grid node from two slots under the log option: the rule in t with
+// weights (w0, wd0, w1, wd1) on value and derivative applied to log R and
+// (dR/dt)/R, or `plain` when a value read is <= 0.
+template <class HP>
+__device__ __forceinline__ double log_rule_node(const HP& v0, bool st0, const HP& v1, bool st1, double w0, double wd0,
+                                                double w1, double wd1, double plain) {
+    const double r0 = st0 ? double(v0.r) + double(v0.dr) : double(v0.r);
+    const double r1 = st1 ? double(v1.r) + double(v1.dr) : double(v1.r);
+    if (!(r0 > 0.0) || !(r1 > 0.0)) return plain;
+    double l = w0 * log(r0) + w1 * log(r1);
+    if (!st0) l += wd0 * double(v0.dr) / r0;
+    if (!st1) l += wd1 * double(v1.dr) / r1;
+    return exp(l);
+}
+
 // largest m in [lo, hi-1] with t[m] <= x, given t[lo] <= x <= t[hi]
 __device__ __forceinline__ int bracket(const double* t, int lo, int hi, double x) {
     while (hi - lo > 1) {
@@ -255,22 +363,34 @@ constexpr int kRowsPerWave = 8;
 static_assert(kRowsPerBlock % kRowsPerWave == 0, "rows per wave");
 constexpr int kColsPerWave = kWave / kRowsPerWave;
 constexpr int kGroups = kRowsPerBlock / kRowsPerWave;  // row groups of a block
+#ifndef GEN_PHASES
+#define GEN_PHASES 4
+#endif
+#ifndef GEN_PHASES_FH
+#define GEN_PHASES_FH 8
+#endif
 
 // Tile configuration per history storage type, chosen by measurement at the
 // L = 4096 workload.  FP64: 12 waves per block (3 per SIMD, 125 VGPRs) with the
 // 2-D stencil issued first in the iteration, so its gathers overlap the
 // stage-slice stencils; FP32: 8 waves per block with the stage-slice stencils
 // first.
-template <class HP> struct HistCfg;
-template <> struct HistCfg<HPoint> {
+template <class HP, int VAR = 0> struct HistCfg {
+    // The other theta schemes and the log-R option hold more values per pair:
+    // fewer waves per block leave each wave the registers to do so without
+    // spilling (index Floater-Hormann: 2 waves per SIMD; theta and log: 1).
+    static constexpr int phases = VAR == 2 ? GEN_PHASES_FH : GEN_PHASES;
+    static constexpr bool d_first = false;
+};
+template <> struct HistCfg<HPoint, 0> {
     static constexpr int phases = 12;
     static constexpr bool d_first = true;
 };
-template <> struct HistCfg<HPoint32> {
+template <> struct HistCfg<HPoint32, 0> {
     static constexpr int phases = 8;
     static constexpr bool d_first = false;
 };
-template <class HP> constexpr int hist_threads() { return kGroups * HistCfg<HP>::phases * kWave; }
+template <class HP, int VAR = 0> constexpr int hist_threads() { return kGroups * HistCfg<HP, VAR>::phases * kWave; }
 
 // Per pair (i, j) the kernel forms
 //   a = (C,R)(t, theta_i theta_j t)        index Lagrange on the stage slice
@@ -291,21 +411,22 @@ __host__ __device__ inline size_t lds_offset_y(int nb) {
 __host__ __device__ inline size_t lds_offset_red(int nb, int L, bool yl) {
     return lds_offset_y(nb) + (yl ? size_t(L) * 16 : 0);
 }
-template <class HP>
+template <class HP, int VAR = 0>
 __host__ __device__ inline size_t lds_bytes(int nb, int L, bool yl) {
-    constexpr int ph = HistCfg<HP>::phases;
+    constexpr int ph = HistCfg<HP, VAR>::phases;
     return lds_offset_red(nb, L, yl) + (ph > 1 ? size_t(kRowsPerBlock) * ph * 9 * 8 : 0);
 }
 
-template <int S, int PM, class HP, bool YL>
+template <int S, int PM, class HP, bool YL, int VAR>
 __device__ __forceinline__ void hist_integral_block(const StageArgs& a, int row_block) {
+    constexpr bool GEN = VAR != kVarDefault;
     // All arithmetic is FP64, also on an FP32 history: values are widened as
     // they are loaded.  (FP32 arithmetic is no faster than FP64 on this chip
     // without packed instructions, and its rounding, unlike the rounding of the
     // stored values, differs from stage to stage and would reach the embedded
     // error estimate.)
     using HS = hreal_t<HP>;  // storage type of the history
-    constexpr int kPhases = HistCfg<HP>::phases;
+    constexpr int kPhases = HistCfg<HP, VAR>::phases;
     constexpr int kColStride = kColsPerWave * kPhases;  // nodes one block iteration covers
     extern __shared__ double smem[];
     const int nb = a.nb;
@@ -392,6 +513,8 @@ __device__ __forceinline__ void hist_integral_block(const StageArgs& a, int row_
         cw0 = 1.0, cw1 = 0.0, cw2 = 0.0, cw3 = 0.0;
         c0p = c1p = slot0;
     }
+    const bool c0s = c0p == stage, c1s = c1p == stage;  // slots without a derivative (log option)
+    constexpr bool use_log = var_log(VAR);
     const double* Xa = a.X + size_t(j) * L;          // row j, read forwards
     const double* Xb = a.X + size_t(L - 1 - j) * L;  // row L-1-j, read backwards
     const double* Xdj = a.Xd + size_t(j) * L;
@@ -409,19 +532,36 @@ __device__ __forceinline__ void hist_integral_block(const StageArgs& a, int row_
         auto fam_abc = [&]() {
             // a: (t, theta_i theta_j)
             {
-                const int base = lagrange<S>(xa, L, wl);
-                interp2<S>(ysrc, base, wl, aC, aR);
+                if constexpr (GEN) {
+                    const double thci = a.thc[i];
+                    const int base = stencil_weights<S, VAR>(a, xa, thi * thj, fma(thi, thcj, thci), wl);
+                    interp2<S>(ysrc, base, wl, aC, aR);
+                    if (use_log) aR = log_interp_y<S>(ysrc, base, wl, aR);
+                } else {
+                    const int base = lagrange<S>(xa, L, wl);
+                    interp2<S>(ysrc, base, wl, aC, aR);
+                }
             }
             // b: (t, phi)
             {
-                const int base = lagrange<S>(double(L - 1) - xb, L, wl);
-                interp2<S>(ysrc, base, wl, bC, bR);
+                if constexpr (GEN) {
+                    const double thci = a.thc[i];
+                    const int base = stencil_weights<S, VAR>(a, double(L - 1) - xb, phi, thcj * thci, wl);
+                    interp2<S>(ysrc, base, wl, bC, bR);
+                    if (use_log) bR = log_interp_y<S>(ysrc, base, wl, bR);
+                } else {
+                    const int base = lagrange<S>(double(L - 1) - xb, L, wl);
+                    interp2<S>(ysrc, base, wl, bC, bR);
+                }
             }
             // c: (t', theta_i)
             {
                 const HP v0 = c0p[i], v1 = c1p[i];
                 cC = cw0 * double(v0.c) + cw1 * double(v0.dc) + cw2 * double(v1.c) + cw3 * double(v1.dc);
                 cR = cw0 * double(v0.r) + cw1 * double(v0.dr) + cw2 * double(v1.r) + cw3 * double(v1.dr);
+                if constexpr (GEN) {
+                    if (use_log) cR = log_rule_node(v0, c0s, v1, c1s, cw0, cw1, cw2, cw3, cR);
+                }
             }
             if (i == 0) c0C = cC;
         };
@@ -430,7 +570,17 @@ __device__ __forceinline__ void hist_integral_block(const StageArgs& a, int row_
             // d: (phi t, psi) on two slots chosen by where s = phi t falls
             {
                 double wd[S];
-                const int base = lagrange<S>(xd, L, wd);
+                int base;
+                if constexpr (GEN) {
+                    double psi = 0.0, psic = 1.0;  // psi = 0/0 := 0 at i = j = 0
+                    if (phi > 0.0) {
+                        psi = thj / phi;
+                        psic = thcj * thi / phi;
+                    }
+                    base = stencil_weights<S, VAR>(a, xd, psi, psic, wd);
+                } else {
+                    base = lagrange<S>(xd, L, wd);
+                }
                 const double s = phi * t;
                 const HP* p0;
                 const HP* p1;
@@ -468,9 +618,19 @@ __device__ __forceinline__ void hist_integral_block(const StageArgs& a, int row_
                 interp4<S>(p1, base, wd, c1, r1, dc1, dr1);
                 dC = h00 * c0 + h10 * dc0 + h01 * c1 + h11 * dc1;
                 dR = h00 * r0 + h10 * dr0 + h01 * r1 + h11 * dr1;
+                if constexpr (GEN) {
+                    if (use_log) {
+                        const bool s0 = p0 == stage, s1 = p1 == stage;
+                        double lv0, ld0, lv1, ld1;
+                        const bool pos0 = log_interp_slot<S>(p0, base, wd, s0, lv0, ld0);
+                        const bool pos1 = log_interp_slot<S>(p1, base, wd, s1, lv1, ld1);
+                        if (pos0 && pos1)
+                            dR = exp(h00 * lv0 + (s0 ? 0.0 : h10 * ld0) + h01 * lv1 + (s1 ? 0.0 : h11 * ld1));
+                    }
+                }
             }
         };
-        if constexpr (HistCfg<HP>::d_first) {
+        if constexpr (HistCfg<HP, VAR>::d_first) {
             fam_d();
             fam_abc();
         } else {
@@ -543,9 +703,9 @@ __device__ __forceinline__ void hist_integral_block(const StageArgs& a, int row_
 }
 
 // One instance: the stage arguments travel by value.
-template <int S, int PM, class HP, bool YL>
-__global__ __launch_bounds__(hist_threads<HP>()) void k_hist_integral(const StageArgs a) {
-    hist_integral_block<S, PM, HP, YL>(a, blockIdx.x);
+template <int S, int PM, class HP, bool YL, int VAR>
+__global__ __launch_bounds__((hist_threads<HP, VAR>())) void k_hist_integral(const StageArgs a) {
+    hist_integral_block<S, PM, HP, YL, VAR>(a, blockIdx.x);
 }
 
 // Many instances in one launch (serving): block b belongs to the instance q
@@ -562,7 +722,7 @@ __global__ __launch_bounds__(hist_threads<HP>()) void k_hist_integral_multi(cons
         if (first_block[mid] <= b) lo = mid;
         else hi = mid;
     }
-    hist_integral_block<S, PM, HP, YL>(args[lo], b - first_block[lo]);
+    hist_integral_block<S, PM, HP, YL, kVarDefault>(args[lo], b - first_block[lo]);
 }
 
 // ---------------------------------------------------------------- RK stage combinations
@@ -815,15 +975,34 @@ static void allow_lds(K kernel, size_t bytes) {
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
 }
 
+template <int S, class HP, bool YL, int VAR>
+static void launch_gen(const StageArgs& a, dim3 grid, hipStream_t st) {
+    const size_t lds = lds_bytes<HP, VAR>(a.nb, a.L, YL);
+    allow_lds(k_hist_integral<S, DMFE_MAX_P, HP, YL, VAR>, lds);
+    hipLaunchKernelGGL((k_hist_integral<S, DMFE_MAX_P, HP, YL, VAR>), grid, dim3(hist_threads<HP, VAR>()), lds, st, a);
+}
 template <int S, class HP, bool YL>
 static void launch_hi_shy(const StageArgs& a, size_t lds, hipStream_t st) {
     const dim3 grid(nblk(a.L, kRowsPerBlock)), block(hist_threads<HP>());
-    if (a.m.pmax <= 4) {
-        allow_lds(k_hist_integral<S, 4, HP, YL>, lds);
-        hipLaunchKernelGGL((k_hist_integral<S, 4, HP, YL>), grid, block, lds, st, a);
+    if (a.interp != DMFE_INTERP_INDEX_LAGRANGE || a.log_r) {
+        const bool fh = a.interp == DMFE_INTERP_INDEX_FH;
+        const bool th = a.interp == DMFE_INTERP_THETA_LAGRANGE || a.interp == DMFE_INTERP_THETA_FH;
+        if (!a.log_r) {
+            if (fh) launch_gen<S, HP, YL, kVarIndexFH>(a, grid, st);
+            else launch_gen<S, HP, YL, kVarTheta>(a, grid, st);
+        } else if (fh) {
+            launch_gen<S, HP, YL, kVarIndexFHLog>(a, grid, st);
+        } else if (th) {
+            launch_gen<S, HP, YL, kVarThetaLog>(a, grid, st);
+        } else {
+            launch_gen<S, HP, YL, kVarIndexLagrangeLog>(a, grid, st);
+        }
+    } else if (a.m.pmax <= 4) {
+        allow_lds(k_hist_integral<S, 4, HP, YL, kVarDefault>, lds);
+        hipLaunchKernelGGL((k_hist_integral<S, 4, HP, YL, kVarDefault>), grid, block, lds, st, a);
     } else {
-        allow_lds(k_hist_integral<S, DMFE_MAX_P, HP, YL>, lds);
-        hipLaunchKernelGGL((k_hist_integral<S, DMFE_MAX_P, HP, YL>), grid, block, lds, st, a);
+        allow_lds(k_hist_integral<S, DMFE_MAX_P, HP, YL, kVarDefault>, lds);
+        hipLaunchKernelGGL((k_hist_integral<S, DMFE_MAX_P, HP, YL, kVarDefault>), grid, block, lds, st, a);
     }
 }
 template <int S, class HP>
@@ -845,6 +1024,8 @@ hipError_t launch_hist_integral(const StageArgs& a, int s, hipStream_t st) {
     case 8: return launch_hi_s<8>(a, st);
     case 10: return launch_hi_s<10>(a, st);
     case 12: return launch_hi_s<12>(a, st);
+    case 14: return launch_hi_s<14>(a, st);
+    case 16: return launch_hi_s<16>(a, st);
     default: return hipErrorInvalidValue;
     }
 }

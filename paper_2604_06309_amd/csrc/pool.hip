@@ -344,10 +344,12 @@ dmfe_status dmfe_pool_create(const dmfe_pool_params* pp, const dmfe_resources* r
 dmfe_status dmfe_pool_submit(dmfe_pool* P, const dmfe_params* p, uint64_t* id) {
     if (!P || !p || !id) return DMFE_ERR_INVALID;
     if (p->mode != DMFE_ADAPTIVE) return DMFE_ERR_INVALID;
-    if ((p->s != 0 && p->s != 10)) return DMFE_ERR_UNSUPPORTED;
     size_t bytes = 0;
     const dmfe_status st = dmfe_footprint(p, &bytes);
     if (st != DMFE_OK) return st;
+    // the batched kernel serves the default stencil
+    if ((p->s != 0 && p->s != 10) || p->theta_interp != DMFE_INTERP_INDEX_LAGRANGE || p->log_r != 0)
+        return DMFE_ERR_UNSUPPORTED;
     if (bytes > P->arena_bytes) return DMFE_ERR_NOMEM;
     // one pool serves one history precision (the batched kernel is instantiated per precision)
     for (auto& q : P->live)

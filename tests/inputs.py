@@ -47,3 +47,27 @@ def smooth_stage(th: np.ndarray, t: float, seed: int):
     """Stage slice (C, R) at time t from the same family as smooth_history."""
     C, R, _, _ = smooth_history(th, np.array([t]), seed)
     return C[0], R[0]
+
+
+def sign_changing_history(th: np.ndarray, times: np.ndarray, seed: int):
+    """As smooth_history, but R = exp(-k2 (1-theta) t) cos(w3 (1-theta) t) changes
+    sign where (1-theta) t passes pi/(2 w3): stencils there hold values of both
+    signs.  R = 1 at theta = 1."""
+    rng = np.random.default_rng(seed)
+    k2, w3 = rng.uniform(0.1, 0.3), rng.uniform(0.6, 1.2)
+    C, _, dC, _ = smooth_history(th, times, seed)
+    one = 1.0 - th
+    R, dR = [], []
+    for t in times:
+        e2 = np.exp(-k2 * one * t)
+        R.append(e2 * np.cos(w3 * one * t))
+        dR.append(-one * e2 * (k2 * np.cos(w3 * one * t) + w3 * np.sin(w3 * one * t)))
+    R, dR = np.array(R), np.array(dR)
+    R[:, -1] = 1.0
+    dR[:, -1] = 0.0
+    return C, R, dC, dR
+
+
+def sign_changing_stage(th: np.ndarray, t: float, seed: int):
+    C, R, _, _ = sign_changing_history(th, np.array([t]), seed)
+    return C[0], R[0]

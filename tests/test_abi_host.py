@@ -92,6 +92,19 @@ def test_grid_rejects_bad_params(lib):
     p = pk.make_params({3: 1.0}, 0.5, L=64, s=7)
     with pytest.raises(pk.DmfeError):
         pk.dmfe_grid(p)
+    # theta-stencil options: scheme, Floater-Hormann degree, log flag, stencil size
+    for kw in (dict(theta_interp=4), dict(theta_interp=-1), dict(theta_interp=pk.INTERP_INDEX_FH, fh_d=10),
+               dict(theta_interp=pk.INTERP_THETA_FH, fh_d=-1), dict(s=18), dict(s=2)):
+        with pytest.raises(pk.DmfeError) as e:
+            pk.dmfe_grid(pk.make_params({3: 1.0}, 0.5, L=64, **kw))
+        assert e.value.status == pk.ERR_INVALID, kw
+    p = pk.make_params({3: 1.0}, 0.5, L=64)
+    p.log_r = 2
+    with pytest.raises(pk.DmfeError):
+        pk.dmfe_grid(p)
+    for kw in (dict(s=16), dict(theta_interp=pk.INTERP_THETA_FH, s=14, fh_d=13), dict(log_r=True),
+               dict(theta_interp=pk.INTERP_INDEX_LAGRANGE, fh_d=99)):  # fh_d is read by the FH schemes only
+        pk.dmfe_grid(pk.make_params({3: 1.0}, 0.5, L=64, **kw))
 
 
 def _ctl(eps=1e-8, dt=0.1, rho=4.0, M=20, scheme=0, policy=0, dt_min=1e-9):
@@ -162,6 +175,12 @@ def test_footprint(lib):
     assert hist + coords <= fp < (hist + coords) * 1.01
     p32 = pk.make_params({3: 0.5, 4: 0.5}, 0.55, t_max=1e7, L=4096, precision=pk.FP32_COMP)
     assert fp - pk.dmfe_footprint(p32) == hist // 2
+    # the barycentric coefficient table of the other theta schemes: (L-s+1) rows of s+1
+    for interp in (pk.INTERP_THETA_LAGRANGE, pk.INTERP_INDEX_FH, pk.INTERP_THETA_FH):
+        pt = pk.make_params({3: 0.5, 4: 0.5}, 0.55, t_max=1e7, L=4096, theta_interp=interp, s=12)
+        extra = pk.dmfe_footprint(pt) - pk.dmfe_footprint(pk.make_params({3: 0.5, 4: 0.5}, 0.55, t_max=1e7, L=4096,
+                                                                          s=12))
+        assert (4096 - 12 + 1) * 13 * 8 <= extra < (4096 - 12 + 1) * 13 * 8 + 512
     pu = pk.make_params({3: 1.0}, 0.5, mode=pk.UNIFORM, h=0.05, N=1000)
     assert pk.dmfe_footprint(pu) >= 2 * 1001 * 1002 // 2 * 8
 

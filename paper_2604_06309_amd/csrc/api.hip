@@ -127,6 +127,7 @@ Layout make_layout(const dmfe_params& p) {
         const size_t L = size_t(p.L), Mc = size_t(p.M_cap > 0 ? p.M_cap : p.L);
         // Mc history slots and the stage slot after them
         lo.hist = take((Mc + 1) * L * (p.precision == DMFE_FP32_COMP ? sizeof(HPoint32) : sizeof(HPoint)));
+        lo.lhist = take(p.log_r ? (Mc + 1) * L * sizeof(LogPoint) : 0);
         lo.thist = take(Mc * sizeof(double));
         lo.slot = take(Mc * sizeof(int));
         lo.th = take(L * sizeof(double));
@@ -288,15 +289,26 @@ StageArgs stage_args(const dmfe_handle* h, double t, int nb, const YPoint* y, YP
     a.log_r = h->p.log_r;
     a.bw = h->at<double>(h->lo.bw);
     for (int k = 0; k < 16; ++k) a.fh_c[k] = h->fh_c[k];
+    a.lhist = log_mirror(h);
     a.m = h->m;
     return a;
+}
+
+LogPoint* log_mirror(const dmfe_handle* h) { return h->p.log_r ? h->at<LogPoint>(h->lo.lhist) : nullptr; }
+
+dmfe_status rebuild_log_mirror(dmfe_handle* h) {
+    if (!h->p.log_r) return DMFE_OK;
+    HCHK(launch_log_mirror(h->L, h->M, h->at<int>(h->lo.slot), h->at<void>(h->lo.hist), h->fp32, log_mirror(h),
+                           h->stream));
+    return DMFE_OK;
 }
 
 // one right-hand-side evaluation: mu(t) then the history integrals
 dmfe_status eval_rhs(dmfe_handle* h, double t, int nb, const YPoint* y, YPoint* kout, void* store) {
     auto* e1 = timing_begin(h, DMFE_K_STAGE_PREP, 0);
+    LogPoint* lm = log_mirror(h);
     HCHK(launch_stage_prep(h->m, h->L, t, h->at<double>(h->lo.nu), y, h->at<double>(h->lo.mue), stage_slot(h),
-                           h->fp32, h->stream));
+                           h->fp32, lm ? lm + size_t(h->Mc) * h->L : nullptr, h->stream));
     timing_end(h, e1);
     auto* e2 = timing_begin(h, DMFE_K_HIST_INTEGRAL, nb);
     HCHK(launch_hist_integral(stage_args(h, t, nb, y, kout, store), h->s, h->stream));
@@ -473,7 +485,9 @@ dmfe_status step_decide(dmfe_handle* h, double err) {
     if (acc) {
         const int slot = c.next_slot;
         h->free_slots.pop_back();
-        HCHK(launch_append(L, h->at<YPoint>(h->lo.ynew), slot_ptr(h, slot), h->fp32, h->stream));
+        LogPoint* lm = log_mirror(h);
+        HCHK(launch_append(L, h->at<YPoint>(h->lo.ynew), slot_ptr(h, slot), h->fp32,
+                           lm ? lm + size_t(slot) * L : nullptr, h->stream));
         h->thist.push_back(tn + dt);
         h->slot.push_back(slot);
         h->M = M + 1;
@@ -799,7 +813,8 @@ dmfe_status dmfe_create(const dmfe_params* params, const dmfe_resources* res, dm
         (e = hipMemcpyAsync(h->at<YPoint>(h->lo.y), y0.data(), sizeof(YPoint) * L, hipMemcpyHostToDevice,
                             h->stream)))
         return bail(fail(e, "hipMemcpyAsync"));
-    const dmfe_status us = upload_order(h);
+    dmfe_status us = upload_order(h);
+    if (us == DMFE_OK) us = rebuild_log_mirror(h);
     if (us != DMFE_OK) return bail(us);
     *out = h;
     return DMFE_OK;
@@ -895,6 +910,8 @@ dmfe_status dmfe_set_history(dmfe_handle* h, int64_t M, int64_t nb, const double
                             hipMemcpyHostToDevice, h->stream));
         HCHK(hipStreamSynchronize(h->stream));
     }
+    const dmfe_status ms = rebuild_log_mirror(h);
+    if (ms != DMFE_OK) return ms;
     HCHK(launch_load_state(L, slot_ptr(h, h->slot[M - 1]), h->fp32, h->at<YPoint>(h->lo.y), h->stream));
     HCHK(hipStreamSynchronize(h->stream));
     h->nb_valid = int(nb);

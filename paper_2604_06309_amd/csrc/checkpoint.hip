@@ -223,6 +223,7 @@ dmfe_status dmfe_checkpoint_load(const char* path, const dmfe_resources* res, dm
     if ((e = hipMemcpyAsync(slot_ptr(h, 0), q, size_t(M) * L * pb, hipMemcpyHostToDevice, h->stream)) != hipSuccess)
         return bail(fail(e, "hipMemcpyAsync"));
     st = upload_order(h);  // also finishes the copies above before the payload goes away
+    if (st == DMFE_OK) st = rebuild_log_mirror(h);  // log-R option: a function of the stored values
     if (st != DMFE_OK) return bail(st);
     *out = h;
     return DMFE_OK;

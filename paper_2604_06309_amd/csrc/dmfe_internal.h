@@ -43,6 +43,13 @@ struct alignas(16) YPoint {
     double c, r;
 };
 
+// log-R option (Appendix A): log R and the scaled derivative (dR/dt)/R of one
+// stored point, computed once per point from the stored values; NaN where R <= 0,
+// so that a stencil holding such a point falls back to R itself.
+struct alignas(16) LogPoint {
+    double lr, lg;
+};
+
 // Arguments of one right-hand-side evaluation on the theta grid.
 struct StageArgs {
     int L;
@@ -69,6 +76,7 @@ struct StageArgs {
     int log_r;           // interpolate log R (falls back to R on non-positive stencils)
     const double* bw;    // barycentric stencil coefficients [L-s+1][s+1] (schemes other than index Lagrange)
     double fh_c[16];     // index Floater-Hormann: the coefficients, the same for every stencil base
+    LogPoint* lhist;     // log-R option: log mirror of the history slots and the stage slot [M_cap+1][L], else null
 };
 
 // Run-constant data of the theta grid used by the coordinate precompute.
@@ -86,14 +94,17 @@ struct GridArgs {
 // launchers (kernels_theta.hip); all return hipError_t of the launch
 hipError_t launch_coords(const GridArgs& g, hipStream_t st);
 hipError_t launch_stage_prep(const Model& m, int L, double t, const double* nu, const YPoint* y, double* mue,
-                             void* stage, int fp32, hipStream_t st);
+                             void* stage, int fp32, LogPoint* lstage, hipStream_t st);
 hipError_t launch_hist_integral(const StageArgs& a, int s, hipStream_t st);
 hipError_t launch_rk_combine(int L, const YPoint* y0, const YPoint* k, int nk, const double* coef, double dt,
                              YPoint* ys, hipStream_t st);
 hipError_t launch_rk_finish(int L, const YPoint* y0, const YPoint* k, int nk, const double* b, const double* e,
                             double dt, YPoint* ynew, double* eps_out, hipStream_t st);
 // History pointers below are HPoint* when fp32 == 0 and HPoint32* when fp32 == 1.
-hipError_t launch_append(int L, const YPoint* y, void* slot_dst, int fp32, hipStream_t st);
+hipError_t launch_append(int L, const YPoint* y, void* slot_dst, int fp32, LogPoint* lslot, hipStream_t st);
+// the log mirror of `count` stored slices (log-R option) from their stored values
+hipError_t launch_log_mirror(int L, int count, const int* slot, const void* hist, int fp32, LogPoint* lhist,
+                             hipStream_t st);
 hipError_t launch_load_state(int L, const void* slot_src, int fp32, YPoint* y, hipStream_t st);
 hipError_t launch_sparsify_residual(int L, int first, int count, const double* thist, const int* slot,
                                     const void* hist, int fp32, double* eps_n, hipStream_t st);

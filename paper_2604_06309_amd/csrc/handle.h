@@ -21,7 +21,7 @@ struct Tableau {
 };
 
 struct Layout {
-    size_t hist, thist, slot, th, thc, nu, bw, X, Xd, y, ys, ynew, k, mue, eps, diag, eps_n, obs, rhs_y, rhs_k, io, total;
+    size_t hist, lhist, thist, slot, th, thc, nu, bw, X, Xd, y, ys, ynew, k, mue, eps, diag, eps_n, obs, rhs_y, rhs_k, io, total;
     // uniform
     size_t uC, uR, uE, uy0, uy1, uys, uk;
 };
@@ -120,6 +120,8 @@ void timing_drain(dmfe_handle* h);
 
 StageArgs stage_args(const dmfe_handle* h, double t, int nb, const YPoint* y, YPoint* kout, void* store);
 void* stage_slot(const dmfe_handle* h);  // the stage slice in history format, after the Mc slots
+LogPoint* log_mirror(const dmfe_handle* h);  // log-R option: mirror of the Mc slots and the stage slot, else null
+dmfe_status rebuild_log_mirror(dmfe_handle* h);  // mirror of the M stored slices from their stored values
 dmfe_status eval_rhs(dmfe_handle* h, double t, int nb, const YPoint* y, YPoint* kout, void* store);
 size_t point_bytes(const dmfe_handle* h);
 void* slot_ptr(dmfe_handle* h, int slot);

@@ -213,52 +213,32 @@ __device__ __forceinline__ int stencil_weights(const StageArgs& a, double x, dou
     return base;
 }
 
-// The log-R option (Appendix A): log R is interpolated with the same weights and
-// exponentiated; a target with a stencil value R <= 0 keeps the plain value.
-template <int S>
-__device__ __forceinline__ double log_interp_y(const YPoint* row, int base, const double (&w)[S], double plain) {
-    double l = 0.0;
-    bool pos = true;
-#pragma unroll
-    for (int k = 0; k < S; ++k) {
-        const double r = row[base + k].r;
-        pos = pos && r > 0.0;
-        l = fma(w[k], log(r), l);  // not used when some r <= 0
-    }
-    return pos ? exp(l) : plain;
+// The log-R option (Appendix A) reads the log mirror: log R and (dR/dt)/R of every
+// stored point, formed once when the point is stored (NaN where R <= 0).  A
+// value is interpolated in log R with the same weights and exponentiated; a NaN
+// in any point read (a non-positive R) leaves the plain value.
+__device__ __forceinline__ LogPoint log_point(double r, double dr) {
+    const double nan = __builtin_nan("");
+    return r > 0.0 ? LogPoint{log(r), dr / r} : LogPoint{nan, nan};
 }
-// One slot of the history under the log option: the theta-interpolated log R
-// and scaled derivative (dR/dt)/R.  The stage slot carries no derivative: its
-// two R fields hold the value (FP64: R and 0; FP32: R and its remainder).
-template <int S, class HP>
-__device__ __forceinline__ bool log_interp_slot(const HP* row, int base, const double (&w)[S], bool stage,
-                                                double& lv, double& ld) {
+template <int S>
+__device__ __forceinline__ double log_interp_stage(const LogPoint* row, int base, const double (&w)[S], double plain) {
+    double l = 0.0;
+#pragma unroll
+    for (int k = 0; k < S; ++k) l = fma(w[k], row[base + k].lr, l);
+    return __builtin_isnan(l) ? plain : exp(l);
+}
+template <int S>
+__device__ __forceinline__ void log_interp_slot(const LogPoint* row, int base, const double (&w)[S], double& lv,
+                                                double& ld) {
     lv = 0.0;
     ld = 0.0;
-    bool pos = true;
 #pragma unroll
     for (int k = 0; k < S; ++k) {
-        const HP v = row[base + k];
-        const double r = stage ? double(v.r) + double(v.dr) : double(v.r);
-        pos = pos && r > 0.0;
-        lv = fma(w[k], log(r), lv);
-        if (!stage) ld = fma(w[k], double(v.dr) / r, ld);
+        const LogPoint q = row[base + k];
+        lv = fma(w[k], q.lr, lv);
+        ld = fma(w[k], q.lg, ld);
     }
-    return pos;
-}
-// R at a grid node from two slots under the log option: the rule in t with
-// weights (w0, wd0, w1, wd1) on value and derivative applied to log R and
-// (dR/dt)/R, or `plain` when a value read is <= 0.
-template <class HP>
-__device__ __forceinline__ double log_rule_node(const HP& v0, bool st0, const HP& v1, bool st1, double w0, double wd0,
-                                                double w1, double wd1, double plain) {
-    const double r0 = st0 ? double(v0.r) + double(v0.dr) : double(v0.r);
-    const double r1 = st1 ? double(v1.r) + double(v1.dr) : double(v1.r);
-    if (!(r0 > 0.0) || !(r1 > 0.0)) return plain;
-    double l = w0 * log(r0) + w1 * log(r1);
-    if (!st0) l += wd0 * double(v0.dr) / r0;
-    if (!st1) l += wd1 * double(v1.dr) / r1;
-    return exp(l);
 }
 
 // largest m in [lo, hi-1] with t[m] <= x, given t[lo] <= x <= t[hi]
@@ -291,12 +271,13 @@ __device__ __forceinline__ void write_stage_point(void* stage, int fp32, int i, 
 template <int PM>
 __device__ __forceinline__ void stage_prep_body(const Model& m, int L, double t, const double* __restrict__ nu,
                                                 const YPoint* __restrict__ y, double* __restrict__ mue, void* stage,
-                                                int fp32) {
+                                                int fp32, LogPoint* lstage = nullptr) {
     __shared__ double sh[16];
     double sk = 0.0, se = 0.0;
     for (int i = threadIdx.x; i < L; i += blockDim.x) {
         const YPoint v = y[i];
         write_stage_point(stage, fp32, i, v);
+        if (lstage) lstage[i] = log_point(v.r, 0.0);  // the stage slice carries no derivative
         const double d1 = fD1<PM>(m, v.c), d2 = fD2<PM>(m, v.c);
         sk = fma(nu[i], d2 * v.r * v.c + d1 * v.r, sk);
         se = fma(nu[i], d1 * v.r, se);
@@ -312,8 +293,8 @@ __device__ __forceinline__ void stage_prep_body(const Model& m, int L, double t,
 template <int PM>
 __global__ __launch_bounds__(1024) void k_stage_prep(const Model m, int L, double t, const double* __restrict__ nu,
                                                      const YPoint* __restrict__ y, double* __restrict__ mue,
-                                                     void* stage, int fp32) {
-    stage_prep_body<PM>(m, L, t, nu, y, mue, stage, fp32);
+                                                     void* stage, int fp32, LogPoint* lstage) {
+    stage_prep_body<PM>(m, L, t, nu, y, mue, stage, fp32, lstage);
 }
 template <int PM>
 __global__ __launch_bounds__(1024) void k_stage_prep_multi(const PrepDesc* __restrict__ d) {
@@ -513,8 +494,11 @@ __device__ __forceinline__ void hist_integral_block(const StageArgs& a, int row_
         cw0 = 1.0, cw1 = 0.0, cw2 = 0.0, cw3 = 0.0;
         c0p = c1p = slot0;
     }
-    const bool c0s = c0p == stage, c1s = c1p == stage;  // slots without a derivative (log option)
     constexpr bool use_log = var_log(VAR);
+    // log mirror rows of the stage slot and of the row's two slots (same offsets as the history)
+    const LogPoint* lstage = use_log ? a.lhist + (stage - hist) : nullptr;
+    const LogPoint* lc0 = use_log ? a.lhist + (c0p - hist) : nullptr;
+    const LogPoint* lc1 = use_log ? a.lhist + (c1p - hist) : nullptr;
     const double* Xa = a.X + size_t(j) * L;          // row j, read forwards
     const double* Xb = a.X + size_t(L - 1 - j) * L;  // row L-1-j, read backwards
     const double* Xdj = a.Xd + size_t(j) * L;
@@ -536,7 +520,7 @@ __device__ __forceinline__ void hist_integral_block(const StageArgs& a, int row_
                     const double thci = a.thc[i];
                     const int base = stencil_weights<S, VAR>(a, xa, thi * thj, fma(thi, thcj, thci), wl);
                     interp2<S>(ysrc, base, wl, aC, aR);
-                    if (use_log) aR = log_interp_y<S>(ysrc, base, wl, aR);
+                    if constexpr (use_log) aR = log_interp_stage<S>(lstage, base, wl, aR);
                 } else {
                     const int base = lagrange<S>(xa, L, wl);
                     interp2<S>(ysrc, base, wl, aC, aR);
@@ -548,7 +532,7 @@ __device__ __forceinline__ void hist_integral_block(const StageArgs& a, int row_
                     const double thci = a.thc[i];
                     const int base = stencil_weights<S, VAR>(a, double(L - 1) - xb, phi, thcj * thci, wl);
                     interp2<S>(ysrc, base, wl, bC, bR);
-                    if (use_log) bR = log_interp_y<S>(ysrc, base, wl, bR);
+                    if constexpr (use_log) bR = log_interp_stage<S>(lstage, base, wl, bR);
                 } else {
                     const int base = lagrange<S>(double(L - 1) - xb, L, wl);
                     interp2<S>(ysrc, base, wl, bC, bR);
@@ -559,8 +543,11 @@ __device__ __forceinline__ void hist_integral_block(const StageArgs& a, int row_
                 const HP v0 = c0p[i], v1 = c1p[i];
                 cC = cw0 * double(v0.c) + cw1 * double(v0.dc) + cw2 * double(v1.c) + cw3 * double(v1.dc);
                 cR = cw0 * double(v0.r) + cw1 * double(v0.dr) + cw2 * double(v1.r) + cw3 * double(v1.dr);
-                if constexpr (GEN) {
-                    if (use_log) cR = log_rule_node(v0, c0s, v1, c1s, cw0, cw1, cw2, cw3, cR);
+                if constexpr (use_log) {
+                    // the stage slot's mirror holds a zero derivative: the same four weights apply
+                    const LogPoint q0 = lc0[i], q1 = lc1[i];
+                    const double l = cw0 * q0.lr + cw1 * q0.lg + cw2 * q1.lr + cw3 * q1.lg;
+                    if (!__builtin_isnan(l)) cR = exp(l);
                 }
             }
             if (i == 0) c0C = cC;
@@ -618,15 +605,12 @@ __device__ __forceinline__ void hist_integral_block(const StageArgs& a, int row_
                 interp4<S>(p1, base, wd, c1, r1, dc1, dr1);
                 dC = h00 * c0 + h10 * dc0 + h01 * c1 + h11 * dc1;
                 dR = h00 * r0 + h10 * dr0 + h01 * r1 + h11 * dr1;
-                if constexpr (GEN) {
-                    if (use_log) {
-                        const bool s0 = p0 == stage, s1 = p1 == stage;
-                        double lv0, ld0, lv1, ld1;
-                        const bool pos0 = log_interp_slot<S>(p0, base, wd, s0, lv0, ld0);
-                        const bool pos1 = log_interp_slot<S>(p1, base, wd, s1, lv1, ld1);
-                        if (pos0 && pos1)
-                            dR = exp(h00 * lv0 + (s0 ? 0.0 : h10 * ld0) + h01 * lv1 + (s1 ? 0.0 : h11 * ld1));
-                    }
+                if constexpr (use_log) {
+                    double lv0, ld0, lv1, ld1;
+                    log_interp_slot<S>(a.lhist + (p0 - hist), base, wd, lv0, ld0);
+                    log_interp_slot<S>(a.lhist + (p1 - hist), base, wd, lv1, ld1);
+                    const double l = h00 * lv0 + h10 * ld0 + h01 * lv1 + h11 * ld1;
+                    if (!__builtin_isnan(l)) dR = exp(l);
                 }
             }
         };
@@ -698,6 +682,9 @@ __device__ __forceinline__ void hist_integral_block(const StageArgs& a, int row_
             HP* st = static_cast<HP*>(a.store);
             st[j].dc = HS(oc);
             st[j].dr = HS(orr);
+            // the log mirror of the slot from its stored values (a slice not yet appended
+            // gets it again when it is)
+            if constexpr (use_log) a.lhist[(st - hist) + j] = log_point(double(st[j].r), double(HS(orr)));
         }
     }
 }
@@ -799,11 +786,24 @@ __global__ __launch_bounds__(1024) void k_rk_finish_multi(const FinishDesc* __re
 }
 
 template <class HP>
-__global__ void k_append(int L, const YPoint* __restrict__ y, HP* __restrict__ dst) {
+__global__ void k_append(int L, const YPoint* __restrict__ y, HP* __restrict__ dst, LogPoint* __restrict__ lm) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= L) return;
+    const hreal_t<HP> r = hreal_t<HP>(y[i].r);
     dst[i].c = hreal_t<HP>(y[i].c);
-    dst[i].r = hreal_t<HP>(y[i].r);
+    dst[i].r = r;
+    // log mirror from the stored values; dr is the derivative a first-same-as-last
+    // stage stored already, else a placeholder the next first stage overwrites
+    if (lm) lm[i] = log_point(double(r), double(dst[i].dr));
+}
+
+template <class HP>
+__global__ void k_log_mirror(int L, int count, const int* __restrict__ slot, const HP* __restrict__ hist,
+                             LogPoint* __restrict__ lhist) {
+    const size_t idx = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= size_t(count) * L) return;
+    const size_t off = size_t(slot[idx / L]) * L + idx % L;
+    lhist[off] = log_point(double(hist[off].r), double(hist[off].dr));
 }
 
 template <class HP>
@@ -947,11 +947,12 @@ hipError_t launch_coords(const GridArgs& g, hipStream_t st) {
 }
 
 hipError_t launch_stage_prep(const Model& m, int L, double t, const double* nu, const YPoint* y, double* mue,
-                             void* stage, int fp32, hipStream_t st) {
+                             void* stage, int fp32, LogPoint* lstage, hipStream_t st) {
     if (m.pmax <= 4)
-        hipLaunchKernelGGL(k_stage_prep<4>, dim3(1), dim3(1024), 0, st, m, L, t, nu, y, mue, stage, fp32);
+        hipLaunchKernelGGL(k_stage_prep<4>, dim3(1), dim3(1024), 0, st, m, L, t, nu, y, mue, stage, fp32, lstage);
     else
-        hipLaunchKernelGGL(k_stage_prep<DMFE_MAX_P>, dim3(1), dim3(1024), 0, st, m, L, t, nu, y, mue, stage, fp32);
+        hipLaunchKernelGGL(k_stage_prep<DMFE_MAX_P>, dim3(1), dim3(1024), 0, st, m, L, t, nu, y, mue, stage, fp32,
+                           lstage);
     return hipGetLastError();
 }
 
@@ -1049,12 +1050,26 @@ hipError_t launch_rk_finish(int L, const YPoint* y0, const YPoint* k, int nk, co
     return hipGetLastError();
 }
 
-hipError_t launch_append(int L, const YPoint* y, void* slot_dst, int fp32, hipStream_t st) {
+hipError_t launch_append(int L, const YPoint* y, void* slot_dst, int fp32, LogPoint* lslot, hipStream_t st) {
     if (fp32)
         hipLaunchKernelGGL(k_append<HPoint32>, dim3(nblk(L, 256)), dim3(256), 0, st, L, y,
-                           static_cast<HPoint32*>(slot_dst));
+                           static_cast<HPoint32*>(slot_dst), lslot);
     else
-        hipLaunchKernelGGL(k_append<HPoint>, dim3(nblk(L, 256)), dim3(256), 0, st, L, y, static_cast<HPoint*>(slot_dst));
+        hipLaunchKernelGGL(k_append<HPoint>, dim3(nblk(L, 256)), dim3(256), 0, st, L, y, static_cast<HPoint*>(slot_dst),
+                           lslot);
+    return hipGetLastError();
+}
+
+hipError_t launch_log_mirror(int L, int count, const int* slot, const void* hist, int fp32, LogPoint* lhist,
+                             hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    const dim3 g(nblk(size_t(count) * L, 256));
+    if (fp32)
+        hipLaunchKernelGGL(k_log_mirror<HPoint32>, g, dim3(256), 0, st, L, count, slot,
+                           static_cast<const HPoint32*>(hist), lhist);
+    else
+        hipLaunchKernelGGL(k_log_mirror<HPoint>, g, dim3(256), 0, st, L, count, slot, static_cast<const HPoint*>(hist),
+                           lhist);
     return hipGetLastError();
 }
 

@@ -31,15 +31,18 @@ def _same(a, b):
         np.testing.assert_array_equal(x, y)
 
 
-@pytest.mark.parametrize("precision,policy,async_write,n1,n2", [
-    (pk.FP64, 0, False, 300, 560),       # DP5, sparsification at a 400-slice cap before and after the save
-    (pk.FP32_COMP, 0, True, 300, 560),   # FP32 history, asynchronous write
-    (pk.FP64, 1, True, 200, 450),        # SSPRK(10,4) from the start
+@pytest.mark.parametrize("precision,policy,async_write,n1,n2,extra", [
+    (pk.FP64, 0, False, 300, 560, {}),       # DP5, sparsification at a 400-slice cap before and after the save
+    (pk.FP32_COMP, 0, True, 300, 560, {}),   # FP32 history, asynchronous write
+    (pk.FP64, 1, True, 200, 450, {}),        # SSPRK(10,4) from the start
+    # log-R option on a theta Floater-Hormann stencil: the log mirror is rebuilt from the stored slices
+    (pk.FP64, 0, False, 300, 560, dict(theta_interp=pk.INTERP_THETA_FH, fh_d=5, log_r=True)),
+    (pk.FP32_COMP, 1, True, 200, 450, dict(log_r=True)),
 ])
-def test_resume_is_bitwise(tmp_path, precision, policy, async_write, n1, n2):
-    say(f"checkpoint precision={precision} policy={policy} async={async_write}")
+def test_resume_is_bitwise(tmp_path, precision, policy, async_write, n1, n2, extra):
+    say(f"checkpoint precision={precision} policy={policy} async={async_write} {extra}")
     p = pk.make_params({3: 0.5, 4: 0.5}, 0.6, t_max=1e4, L=64, M_cap=400, eps=1e-8, dt0=1e-3, dt_min=1e-12,
-                       precision=precision, scheme_policy=policy)
+                       precision=precision, scheme_policy=policy, **extra)
     path = str(tmp_path / "solve.ckpt")
     ref = pk.Solver(p)
     ref.step(float("inf"), n1)

@@ -381,6 +381,56 @@ def adaptive_c2(pk, torch) -> dict:
             "E_final": float(E[-1]), "trace_steps_t_M_wall": trace}
 
 
+def large_grid_c5(pk, torch, warm_ticks: int = 60, ticks: int = 120) -> dict:
+    """The large-grid stress configuration: 16 identical solves of the 2+4 model
+    (a2^2 = 0.3, a4^2 = 0.7, T = 0.45, t_max = 1e7) on an 8192-point grid, history
+    cap 8192, admitted together into one pool and advanced in batched ticks (one
+    RK stage of every solve per tick).  After warm_ticks, `ticks` ticks are timed
+    between device synchronisations: aggregate stage evaluations per second, and
+    the algorithmic bytes they move (history at the window's mean M, stage slice,
+    output and grid data).  The same solve alone, timed over the same steps, gives
+    the one-instance rate.  FP64 and FP32-comp."""
+    out = {"config": "16 x (2+4 model a2^2=0.3, a4^2=0.7, T=0.45, t_max=1e7), L=8192, history cap 8192, "
+                     "eps=1e-8, one pool, batched ticks"}
+    L = 8192
+    for name, prec in (("fp64", pk.FP64), ("fp32c", pk.FP32_COMP)):
+        p = pk.make_params({2: 0.3, 4: 0.7}, 0.45, t_max=1e7, L=L, M_cap=8192, eps=1e-8, dt0=1e-3, dt_min=1e-12,
+                           precision=prec)
+        pool = pk.Pool(16 * pk.dmfe_footprint(p) + 4096, max_instances=16)
+        ids = [pool.submit(p) for _ in range(16)]
+        pool.run(warm_ticks)
+        torch.cuda.synchronize()
+        m0 = pool.result(ids[0])[0].M
+        t0 = time.perf_counter()
+        st = pool.run(ticks)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        info = pool.result(ids[0])[0]
+        assert st.running == 16
+        pool.close()
+        evals = 16 * ticks
+        mean_M = 0.5 * (m0 + info.M)
+        pb = 32 if prec == pk.FP64 else 16
+        alg = mean_M * L * pb + 2 * 16 * L + 24 * L
+        # one instance alone over the same steps
+        sv = pk.Solver(p)
+        sv.step(float("inf"), warm_ticks // 6)
+        torch.cuda.synchronize()
+        n0 = sv.info().rhs_evals
+        t1 = time.perf_counter()
+        sv.step(float("inf"), ticks // 6)
+        torch.cuda.synchronize()
+        solo_wall = time.perf_counter() - t1
+        solo_evals = sv.info().rhs_evals - n0
+        sv.close()
+        out[name] = {"ticks": ticks, "stage_evals": evals, "wall_s": wall, "stage_evals_per_s": evals / wall,
+                     "mean_M": mean_M, "algorithmic_GBps": evals * alg / wall / 1e9,
+                     "solo_stage_evals_per_s": solo_evals / solo_wall, "t_end": info.t}
+        log(f"C5 {name}: {evals / wall:.1f} stage-evals/s pooled ({evals} in {wall:.2f} s, mean M {mean_M:.0f}); "
+            f"alone {solo_evals / solo_wall:.1f}")
+    return out
+
+
 def aging_p3(pk, torch, t_end: float = 1e4) -> dict:
     """The paper's energy-exponent experiment (Sec. 4.2): pure p=3 (f = q^3/2),
     quench from a random start to T = 0, L = 1024, eps = 1e-10, to t_end.  Reports
@@ -423,6 +473,8 @@ def main() -> int:
     ap.add_argument("--serving", type=int, default=24, help="requests in the serving sweep (0: skip)")
     ap.add_argument("--kernel", action="store_true",
                     help="time the history-integral kernel alone on a synthetic full-size history")
+    ap.add_argument("--c5", action="store_true",
+                    help="only the large-grid configuration: 16 solves at L=8192 in one pool")
     ap.add_argument("--stencils", action="store_true",
                     help="only the cost and accuracy of the theta-stencil schemes and the log-R option")
     ap.add_argument("--kernel-slices", type=int, default=2500,
@@ -444,6 +496,9 @@ def main() -> int:
         return 0
     if args.stencils:
         print(json.dumps(stencil_sweep(pk, torch, args)), flush=True)
+        return 0
+    if args.c5:
+        print(json.dumps(large_grid_c5(pk, torch)), flush=True)
         return 0
     prec_name = args.precision
     other = "fp32c" if prec_name == "fp64" else "fp64"

@@ -344,12 +344,7 @@ constexpr int kRowsPerWave = 8;
 static_assert(kRowsPerBlock % kRowsPerWave == 0, "rows per wave");
 constexpr int kColsPerWave = kWave / kRowsPerWave;
 constexpr int kGroups = kRowsPerBlock / kRowsPerWave;  // row groups of a block
-#ifndef GEN_PHASES
-#define GEN_PHASES 4
-#endif
-#ifndef GEN_PHASES_FH
-#define GEN_PHASES_FH 8
-#endif
+
 
 // Tile configuration per history storage type, chosen by measurement at the
 // L = 4096 workload.  FP64: 12 waves per block (3 per SIMD, 125 VGPRs) with the
@@ -359,8 +354,10 @@ constexpr int kGroups = kRowsPerBlock / kRowsPerWave;  // row groups of a block
 template <class HP, int VAR = 0> struct HistCfg {
     // The other theta schemes and the log-R option hold more values per pair:
     // fewer waves per block leave each wave the registers to do so without
-    // spilling (index Floater-Hormann: 2 waves per SIMD; theta and log: 1).
-    static constexpr int phases = VAR == 2 ? GEN_PHASES_FH : GEN_PHASES;
+    // spilling: 8 waves per block (2 per SIMD) for index Floater-Hormann, 4
+    // (1 per SIMD) for the theta schemes and log R, whose 8-wave builds spill
+    // and run 1.6-2.8x slower at L = 4096.
+    static constexpr int phases = VAR == kVarIndexFH ? 8 : 4;
     static constexpr bool d_first = false;
 };
 template <> struct HistCfg<HPoint, 0> {

@@ -119,6 +119,7 @@ def _check_rhs(gC, gR, oC, oR, gmu, omu, T=0.6):
     (64, 30, 30, 6.0, 1),      # every target inside the stored slices or the last step
     (64, 30, 29, 6.0, 2),      # first stage: last slice without derivative
     (200, 45, 45, 11.0, 3),    # L not a multiple of the wave or block size
+    (203, 45, 45, 11.0, 3),    # L odd: the last row groups of a wave are partly outside the grid
     (1000, 80, 80, 40.0, 4),   # many tiles per row
     (96, 2, 1, 0.3, 5),        # one stored interval
     (96, 1, 1, 0.2, 6),        # only t = 0 stored

@@ -264,6 +264,19 @@ const char *dmfe_status_string(dmfe_status s);
 /* Text of the last HIP failure seen by any handle in this thread ("" if none). */
 const char *dmfe_last_error(void);
 
+/*
+ * Human-readable parameter record of a solve (Appendix A: each run records
+ * what reproduces it).  One "key = value" line per item: the library's source
+ * revision and compiler, the HIP runtime and device, the process command line,
+ * every field of dmfe_params, the grid-generation values (gamma, the grid
+ * parameters) and the solve's current state and counters.
+ * buf (host memory, cap bytes, may be NULL when cap is 0) receives the text
+ * with a terminating NUL; *needed (if not NULL) the bytes that requires.
+ * DMFE_ERR_BUFFER when cap is too small (buf untouched); DMFE_ERR_INVALID for
+ * a NULL handle.  Reads host state only: no device work is enqueued.
+ */
+dmfe_status dmfe_param_record(const dmfe_handle *h, char *buf, size_t cap, size_t *needed);
+
 /* ---------------------------------------------------------------- checkpoint and resume
  * Long solves (Sec. 4: runs to t ~ 1e7) survive restarts.  A checkpoint holds
  * the parameters (the solve's record), the controller state and counters, the

@@ -98,6 +98,7 @@ SIGNATURES = {
     "dmfe_destroy": (None, [_vp]),
     "dmfe_status_string": (ctypes.c_char_p, [_i32]),
     "dmfe_last_error": (ctypes.c_char_p, []),
+    "dmfe_param_record": (_i32, [_vp, ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
     "dmfe_grid": (_i32, [ctypes.POINTER(dmfe_params), _vp, _vp, _vp, _vp]),
     "dmfe_control_update": (_i32, [ctypes.POINTER(dmfe_control), _d, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "dmfe_sparsify_select": (_i32, [_vp, _i64, _i64, _d, _vp, ctypes.POINTER(_i64)]),
@@ -283,6 +284,16 @@ def dmfe_checkpoint_load(path: str, device: int = 0, stream: int = 0, workspace:
 
 def dmfe_status_string(status: int) -> str:
     return lib().dmfe_status_string(status).decode()
+
+
+def dmfe_param_record(h: int) -> str:
+    """The solve's human-readable parameter record (key = value lines)."""
+    need = ctypes.c_size_t()
+    st = lib().dmfe_param_record(h, None, 0, ctypes.byref(need))
+    _check(st, "dmfe_param_record", (OK, ERR_BUFFER))
+    buf = ctypes.create_string_buffer(need.value)
+    _check(lib().dmfe_param_record(h, buf, need.value, ctypes.byref(need)), "dmfe_param_record")
+    return buf.value.decode()
 
 
 def dmfe_last_error() -> str:
@@ -479,6 +490,10 @@ class Solver:
 
     def info(self) -> dmfe_step_info:
         return dmfe_get_info(self.h)
+
+    def param_record(self) -> str:
+        """Human-readable record of the solve: library build, device, parameters, grid, state."""
+        return dmfe_param_record(self.h)
 
     def read(self, field: int, first: int = 0, count: Optional[int] = None) -> np.ndarray:
         """Host copy of a field.  Adaptive: C/R/DC/DR -> [count, L]; uniform C/R -> packed rows."""

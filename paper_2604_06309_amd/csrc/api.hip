@@ -617,6 +617,93 @@ const char* dmfe_status_string(dmfe_status s) {
 
 const char* dmfe_last_error(void) { return last_error(); }
 
+dmfe_status dmfe_param_record(const dmfe_handle* h, char* buf, size_t cap, size_t* needed) {
+    if (!h) return DMFE_ERR_INVALID;
+    std::string out;
+    char line[512];
+    auto put = [&](const char* key, const std::string& val) {
+        std::snprintf(line, sizeof(line), "%s = %s\n", key, val.c_str());
+        out += line;
+    };
+    auto num = [](double v) {
+        char b[40];
+        std::snprintf(b, sizeof(b), "%.17g", v);
+        return std::string(b);
+    };
+    auto inum = [](long long v) { return std::to_string(v); };
+    const dmfe_params& p = h->p;
+    out += "# DMFE solve: parameter record\n";
+#ifdef DMFE_SOURCE_REVISION
+    put("library_revision", DMFE_SOURCE_REVISION);
+#else
+    put("library_revision", "unknown");
+#endif
+    put("compiler", __VERSION__);
+    int rt = 0;
+    put("hip_runtime", hipRuntimeGetVersion(&rt) == hipSuccess ? inum(rt) : "unknown");
+    hipDeviceProp_t prop{};
+    if (hipGetDeviceProperties(&prop, h->device) == hipSuccess) {
+        put("device", std::to_string(h->device) + " " + prop.name + " (" + prop.gcnArchName + "), " +
+                          inum(prop.multiProcessorCount) + " CUs, " + num(double(prop.totalGlobalMem) / 1073741824.0) +
+                          " GiB");
+    }
+    {  // the process command line, arguments separated by spaces
+        std::string cmd;
+        if (FILE* f = std::fopen("/proc/self/cmdline", "rb")) {
+            int c;
+            while ((c = std::fgetc(f)) != EOF && cmd.size() < 400) cmd += c == 0 ? ' ' : char(c);
+            std::fclose(f);
+        }
+        while (!cmd.empty() && cmd.back() == ' ') cmd.pop_back();
+        put("command_line", cmd.empty() ? "unknown" : cmd);
+    }
+    put("mode", p.mode == DMFE_ADAPTIVE ? "adaptive" : "uniform");
+    std::string model;
+    for (int k = 0; k < p.n_terms; ++k) model += (k ? " + " : "") + num(p.a2[k]) + " q^" + inum(p.p[k]) + "/2";
+    put("f(q)", model);
+    put("T", num(p.T));
+    put("beta0", num(p.beta0));
+    put("precision", p.precision == DMFE_FP32_COMP ? "fp32-comp" : "fp64");
+    if (p.mode == DMFE_UNIFORM) {
+        put("h", num(p.h));
+        put("N", inum(p.N));
+    } else {
+        static const char* schemes[] = {"index-lagrange", "theta-lagrange", "index-floater-hormann",
+                                        "theta-floater-hormann"};
+        put("t_max", num(p.t_max));
+        put("grid_gamma", num(h->gamma));
+        put("grid_alpha", num(p.grid_alpha));
+        put("grid_delta", num(p.grid_delta));
+        put("L", inum(p.L));
+        put("M_cap", inum(h->Mc));
+        put("eps", num(p.eps));
+        put("dt0", num(p.dt0));
+        put("dt_min", num(p.dt_min));
+        put("s", inum(h->s));
+        put("theta_interp", schemes[p.theta_interp]);
+        if (p.theta_interp == DMFE_INTERP_INDEX_FH || p.theta_interp == DMFE_INTERP_THETA_FH) put("fh_d", inum(p.fh_d));
+        put("log_r", inum(p.log_r));
+        put("auto_passes", inum(p.auto_passes));
+        put("scheme_policy", inum(p.scheme_policy));
+    }
+    dmfe_step_info info{};
+    fill_info(h, &info);
+    put("state_t", num(info.t));
+    put("state_dt", num(info.dt));
+    put("state_M", inum(info.M));
+    put("state_scheme", info.scheme == DMFE_SCHEME_SSPRK104 ? "ssprk104" : "dp5");
+    put("accepted", inum(info.accepted));
+    put("rejected", inum(info.rejected));
+    put("reverts", inum(info.reverts));
+    put("sparsify_calls", inum(info.sparsify_calls));
+    put("removed", inum(info.removed));
+    put("rhs_evals", inum(info.rhs_evals));
+    if (needed) *needed = out.size() + 1;
+    if (cap < out.size() + 1) return DMFE_ERR_BUFFER;
+    std::memcpy(buf, out.c_str(), out.size() + 1);
+    return DMFE_OK;
+}
+
 dmfe_status dmfe_footprint(const dmfe_params* params, size_t* bytes) {
     const dmfe_status v = validate(params);
     if (v != DMFE_OK) return v;

@@ -167,6 +167,11 @@ def test_sparsify_select_matches_oracle(lib):
         assert n1 == n2 and np.array_equal(d1, d2)
 
 
+def test_param_record_needs_a_handle(lib):
+    need = ctypes.c_size_t(7)
+    assert lib.dmfe_param_record(None, None, 0, ctypes.byref(need)) == pk.ERR_INVALID
+
+
 def test_footprint(lib):
     p = pk.make_params({3: 0.5, 4: 0.5}, 0.55, t_max=1e7, L=4096)
     fp = pk.dmfe_footprint(p)

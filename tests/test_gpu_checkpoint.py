@@ -73,3 +73,33 @@ def test_corrupted_checkpoint_is_refused(tmp_path):
     with pytest.raises(pk.DmfeError) as e:
         pk.Solver.load(str(path), p)
     assert e.value.status == pk.ERR_INVALID
+
+
+def test_parameter_record(tmp_path):
+    """The human-readable record of a solve: library build, device, every parameter
+    (round-trip exact), the grid and the state; a resumed solve records the same
+    parameters and state as the one it was saved from."""
+    p = pk.make_params({3: 0.5, 4: 0.5}, 0.6, t_max=1e4, L=64, M_cap=200, eps=1e-8, dt0=1e-3, dt_min=1e-12,
+                       theta_interp=pk.INTERP_THETA_FH, fh_d=5, log_r=True)
+    s = pk.Solver(p)
+    s.step(float("inf"), 40)
+    rec = s.param_record()
+    say(rec)
+    kv = dict(line.split(" = ", 1) for line in rec.splitlines() if " = " in line and not line.startswith("#"))
+    info = s.info()
+    assert kv["library_revision"] and kv["compiler"] and "gfx950" in kv["device"]
+    assert float(kv["T"]) == 0.6 and float(kv["eps"]) == 1e-8 and float(kv["t_max"]) == 1e4
+    assert int(kv["L"]) == 64 and int(kv["M_cap"]) == 200 and int(kv["s"]) == 10
+    assert kv["theta_interp"] == "theta-floater-hormann" and int(kv["fh_d"]) == 5 and int(kv["log_r"]) == 1
+    assert kv["f(q)"] == "0.5 q^3/2 + 0.5 q^4/2"
+    assert int(kv["accepted"]) == info.accepted and float(kv["state_t"]) == info.t and int(kv["state_M"]) == info.M
+    assert float(kv["grid_gamma"]) > 1.0
+    path = str(tmp_path / "rec.ckpt")
+    s.checkpoint(path)
+    s.close()
+    r = pk.Solver.load(path, p)
+    kv2 = dict(line.split(" = ", 1) for line in r.param_record().splitlines() if " = " in line)
+    r.close()
+    for k, v in kv.items():
+        if k not in ("command_line",):
+            assert kv2[k] == v, k

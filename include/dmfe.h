@@ -301,6 +301,22 @@ dmfe_status dmfe_checkpoint_wait(dmfe_handle *h);
  * format or version, inconsistent, truncated or fails its checksum. */
 dmfe_status dmfe_checkpoint_load(const char *path, const dmfe_resources *res, dmfe_handle **out);
 
+/*
+ * Compressed snapshot for post-processing (Appendix A): the history at reduced
+ * resolution, for analyses that do not need all of it.  Kept: every
+ * slice_stride-th stored slice and the newest, every theta_stride-th grid node
+ * and theta = 1 (strides >= 1).  Written (host byte order):
+ *   magic "DMFESNP1", uint32 version 1, uint32 header bytes,
+ *   int64 L, M, theta_stride, slice_stride, L_kept, M_kept, uint64 record bytes,
+ *   the parameter record text (dmfe_param_record, with its NUL),
+ *   theta[L_kept] f64, t[M_kept] f64, E[M_kept] f64, mu[M_kept] f64,
+ *   C[M_kept][L_kept] f32, R[M_kept][L_kept] f32 (rounded from the stored values).
+ * Adaptive mode only (DMFE_ERR_UNSUPPORTED otherwise); DMFE_ERR_INVALID for bad
+ * strides, a step in flight or an unwritable path.  Synchronous: the call
+ * returns after the file is closed.
+ */
+dmfe_status dmfe_snapshot_save(dmfe_handle *h, const char *path, int32_t theta_stride, int32_t slice_stride);
+
 /* ---------------------------------------------------------------- serving pool
  * Many solves (a parameter sweep: different T, a_p, t_max, L) stepped
  * together on one device.  Requests queue on submit and are admitted while a

@@ -99,6 +99,7 @@ SIGNATURES = {
     "dmfe_status_string": (ctypes.c_char_p, [_i32]),
     "dmfe_last_error": (ctypes.c_char_p, []),
     "dmfe_param_record": (_i32, [_vp, ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
+    "dmfe_snapshot_save": (_i32, [_vp, ctypes.c_char_p, _i32, _i32]),
     "dmfe_grid": (_i32, [ctypes.POINTER(dmfe_params), _vp, _vp, _vp, _vp]),
     "dmfe_control_update": (_i32, [ctypes.POINTER(dmfe_control), _d, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "dmfe_sparsify_select": (_i32, [_vp, _i64, _i64, _d, _vp, ctypes.POINTER(_i64)]),
@@ -284,6 +285,32 @@ def dmfe_checkpoint_load(path: str, device: int = 0, stream: int = 0, workspace:
 
 def dmfe_status_string(status: int) -> str:
     return lib().dmfe_status_string(status).decode()
+
+
+def load_snapshot(path: str) -> dict:
+    """Read a file written by dmfe_snapshot_save: theta, t, E, mu (float64), C and R
+    ([M_kept, L_kept] float32), the strides, L, M and the parameter record text."""
+    raw = open(path, "rb").read()
+    if raw[:8] != b"DMFESNP1":
+        raise ValueError(f"{path}: not a DMFE snapshot")
+    version, header = np.frombuffer(raw, np.uint32, 2, 8)
+    if version != 1:
+        raise ValueError(f"{path}: snapshot version {version}")
+    L, M, ts, ss, Lk, Mk = (int(v) for v in np.frombuffer(raw, np.int64, 6, 16))
+    rb = int(np.frombuffer(raw, np.uint64, 1, 64)[0])
+    off = int(header)
+    record = raw[off:off + rb].rstrip(b"\0").decode()
+    off += rb
+    out = {"L": L, "M": M, "theta_stride": ts, "slice_stride": ss, "record": record}
+    for name, n in (("theta", Lk), ("t", Mk), ("E", Mk), ("mu", Mk)):
+        out[name] = np.frombuffer(raw, np.float64, n, off).copy()
+        off += 8 * n
+    for name in ("C", "R"):
+        out[name] = np.frombuffer(raw, np.float32, Mk * Lk, off).reshape(Mk, Lk).copy()
+        off += 4 * Mk * Lk
+    if off != len(raw):
+        raise ValueError(f"{path}: {len(raw) - off} bytes past the snapshot")
+    return out
 
 
 def dmfe_param_record(h: int) -> str:
@@ -494,6 +521,12 @@ class Solver:
     def param_record(self) -> str:
         """Human-readable record of the solve: library build, device, parameters, grid, state."""
         return dmfe_param_record(self.h)
+
+    def snapshot(self, path: str, theta_stride: int = 4, slice_stride: int = 1) -> None:
+        """Compressed snapshot for post-processing (every theta_stride-th node, every
+        slice_stride-th slice, FP32 C and R); read it back with load_snapshot()."""
+        _check(lib().dmfe_snapshot_save(self.h, os.fsencode(path), int(theta_stride), int(slice_stride)),
+               "dmfe_snapshot_save")
 
     def read(self, field: int, first: int = 0, count: Optional[int] = None) -> np.ndarray:
         """Host copy of a field.  Adaptive: C/R/DC/DR -> [count, L]; uniform C/R -> packed rows."""

@@ -229,4 +229,67 @@ dmfe_status dmfe_checkpoint_load(const char* path, const dmfe_resources* res, dm
     return DMFE_OK;
 }
 
+dmfe_status dmfe_snapshot_save(dmfe_handle* h, const char* path, int32_t theta_stride, int32_t slice_stride) {
+    if (!h || !path || theta_stride < 1 || slice_stride < 1) return DMFE_ERR_INVALID;
+    if (h->p.mode != DMFE_ADAPTIVE) return DMFE_ERR_UNSUPPORTED;
+    if (h->cur.active) return fail_msg(DMFE_ERR_INVALID, "snapshot: a step is in flight");
+    const int L = h->L, M = h->M;
+    std::vector<int64_t> nodes, slices;
+    for (int i = 0; i < L; i += theta_stride) nodes.push_back(i);
+    if (nodes.back() != L - 1) nodes.push_back(L - 1);
+    for (int n = 0; n < M; n += slice_stride) slices.push_back(n);
+    if (slices.back() != M - 1) slices.push_back(M - 1);
+    const size_t Lk = nodes.size(), Mk = slices.size();
+    // the full fields through the read path, then the kept rows and columns
+    std::vector<double> th(L), t(M), E(M), mu(M), C(size_t(M) * L), R(size_t(M) * L);
+    struct Part {
+        int32_t field;
+        double* dst;
+        int64_t count;
+    } parts[] = {{DMFE_F_THETA, th.data(), L}, {DMFE_F_T_GRID, t.data(), M}, {DMFE_F_ENERGY, E.data(), M},
+                 {DMFE_F_MU, mu.data(), M},      {DMFE_F_C, C.data(), M},      {DMFE_F_R, R.data(), M}};
+    for (const Part& q : parts) {
+        const size_t bytes = sizeof(double) * size_t(q.count) * (q.field == DMFE_F_C || q.field == DMFE_F_R ? L : 1);
+        const dmfe_status st = dmfe_read(h, q.field, 0, q.count, q.dst, bytes, 0, nullptr);
+        if (st != DMFE_OK) return st;
+    }
+    size_t rec_bytes = 0;
+    dmfe_param_record(h, nullptr, 0, &rec_bytes);
+    std::vector<char> rec(rec_bytes);
+    dmfe_status st = dmfe_param_record(h, rec.data(), rec.size(), &rec_bytes);
+    if (st != DMFE_OK) return st;
+
+    std::vector<unsigned char> out;
+    auto put = [&](const void* p, size_t n) {
+        const unsigned char* b = static_cast<const unsigned char*>(p);
+        out.insert(out.end(), b, b + n);
+    };
+    const char magic[8] = {'D', 'M', 'F', 'E', 'S', 'N', 'P', '1'};
+    const uint32_t version = 1, header = 8 + 4 + 4 + 7 * 8;
+    const int64_t hdr[6] = {L, M, theta_stride, slice_stride, int64_t(Lk), int64_t(Mk)};
+    const uint64_t rb = rec.size();
+    put(magic, 8);
+    put(&version, 4);
+    put(&header, 4);
+    put(hdr, sizeof(hdr));
+    put(&rb, 8);
+    put(rec.data(), rec.size());
+    for (int64_t i : nodes) put(&th[i], 8);
+    for (int64_t n : slices) put(&t[n], 8);
+    for (int64_t n : slices) put(&E[n], 8);
+    for (int64_t n : slices) put(&mu[n], 8);
+    for (const std::vector<double>* f : {&C, &R})
+        for (int64_t n : slices)
+            for (int64_t i : nodes) {
+                const float v = float((*f)[size_t(n) * L + i]);
+                put(&v, 4);
+            }
+    FILE* fp = std::fopen(path, "wb");
+    if (!fp) return fail_msg(DMFE_ERR_INVALID, std::string("snapshot: cannot open ") + path + " for writing");
+    const bool ok = std::fwrite(out.data(), 1, out.size(), fp) == out.size();
+    const bool closed = std::fclose(fp) == 0;
+    if (!ok || !closed) return fail_msg(DMFE_ERR_INVALID, std::string("snapshot: write to ") + path + " failed");
+    return DMFE_OK;
+}
+
 }  // extern "C"

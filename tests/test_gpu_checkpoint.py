@@ -103,3 +103,29 @@ def test_parameter_record(tmp_path):
     for k, v in kv.items():
         if k not in ("command_line",):
             assert kv2[k] == v, k
+
+
+def test_compressed_snapshot(tmp_path):
+    """The post-processing snapshot holds every theta_stride-th node (and theta = 1),
+    every slice_stride-th slice (and the newest), E and mu of those slices exactly,
+    C and R rounded to FP32, and the parameter record."""
+    p = pk.make_params({3: 0.5, 4: 0.5}, 0.6, t_max=1e4, L=64, M_cap=200, eps=1e-8, dt0=1e-3, dt_min=1e-12)
+    s = pk.Solver(p)
+    s.step(float("inf"), 60)
+    path = str(tmp_path / "run.snap")
+    s.snapshot(path, theta_stride=3, slice_stride=4)
+    snap = pk.load_snapshot(path)
+    M = s.info().M
+    nodes = np.unique(np.r_[np.arange(0, 64, 3), 63])
+    slices = np.unique(np.r_[np.arange(0, M, 4), M - 1])
+    np.testing.assert_array_equal(snap["theta"], s.read(pk.F_THETA)[nodes])
+    np.testing.assert_array_equal(snap["t"], s.read(pk.F_T_GRID)[slices])
+    np.testing.assert_array_equal(snap["E"], s.read(pk.F_ENERGY)[slices])
+    np.testing.assert_array_equal(snap["mu"], s.read(pk.F_MU)[slices])
+    np.testing.assert_array_equal(snap["C"], s.read(pk.F_C)[np.ix_(slices, nodes)].astype(np.float32))
+    np.testing.assert_array_equal(snap["R"], s.read(pk.F_R)[np.ix_(slices, nodes)].astype(np.float32))
+    assert (snap["L"], snap["M"], snap["theta_stride"], snap["slice_stride"]) == (64, M, 3, 4)
+    assert "L = 64" in snap["record"] and "state_M = %d" % M in snap["record"]
+    with pytest.raises(pk.DmfeError):
+        s.snapshot(path, theta_stride=0)
+    s.close()

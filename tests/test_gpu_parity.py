@@ -269,3 +269,51 @@ def test_errors_from_device_calls():
     with pytest.raises(pk.DmfeError):
         s.read(pk.F_C, 0, 5)  # only one slice stored
     s.close()
+
+
+# ----------------------------------------------------------------------------- forced failures
+def _reference_history(p, steps):
+    s = pk.Solver(p)
+    s.step(float("inf"), steps)
+    info = s.info()
+    h = [s.read(f) for f in (pk.F_T_GRID, pk.F_C, pk.F_R, pk.F_DC, pk.F_DR)]
+    s.close()
+    return info, h
+
+
+def test_nan_in_the_state_is_reported_not_stepped():
+    """A NaN in the state (forced from the host) makes the error estimate non-finite:
+    the step ends with DMFE_ERR_NONFINITE."""
+    say("forced NaN in the state")
+    p = pk.make_params({3: 0.5, 4: 0.5}, 0.6, t_max=1e4, L=64, M_cap=400, eps=1e-8, dt0=1e-3, dt_min=1e-12)
+    info, (t, C, R, dC, dR) = _reference_history(p, 50)
+    C = C.copy()
+    C[-1, 20] = np.nan
+    s = pk.Solver(p)
+    s.set_history(t, C, R, dC, dR, nb=t.size - 1, dt=info.dt)
+    with pytest.raises(pk.DmfeError) as e:
+        s.step(float("inf"), 5)
+    assert e.value.status == pk.ERR_NONFINITE
+    s.close()
+
+
+def test_forced_revert_keeps_the_earlier_slices_bitwise():
+    """A step 20 times too large (forced through the controller's dt) has an error
+    above 2 eps: it is rejected, the last 10 slices are dropped and dt halved, and
+    the slices kept are bitwise those given before (Sec. 3.5)."""
+    say("forced revert")
+    p = pk.make_params({3: 0.5, 4: 0.5}, 0.6, t_max=1e4, L=64, M_cap=400, eps=1e-8, dt0=1e-3, dt_min=1e-12)
+    info, (t, C, R, dC, dR) = _reference_history(p, 100)
+    M = t.size
+    s = pk.Solver(p)
+    s.set_history(t, C, R, dC, dR, nb=M - 1, dt=20 * info.dt)
+    st, got = s.step(float("inf"), 1)
+    assert (got.accepted, got.rejected, got.reverts) == (0, 1, 10)  # reverts counts the slices dropped
+    assert got.M == M - 10 and got.dt == 10 * info.dt
+    np.testing.assert_array_equal(s.read(pk.F_T_GRID), t[:M - 10])
+    for f, ref in ((pk.F_C, C), (pk.F_R, R), (pk.F_DC, dC), (pk.F_DR, dR)):
+        np.testing.assert_array_equal(s.read(f), ref[:M - 10])
+    # and the solve goes on from there
+    st, got = s.step(float("inf"), 20)
+    assert got.accepted > 0 and np.all(np.isfinite(s.read(pk.F_C)))
+    s.close()

@@ -18,6 +18,11 @@ import paper_2604_06309_amd as pk  # noqa: E402
 pytestmark = pytest.mark.gpu
 
 
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
 def test_energy_exponent_pure_p3_quench_to_zero_temperature():
     p = pk.make_params({3: 1.0}, 0.0, t_max=1e7, L=1024, M_cap=8192, eps=1e-10, dt0=1e-3, dt_min=1e-14)
     s = pk.Solver(p)
@@ -37,3 +42,69 @@ def test_energy_exponent_pure_p3_quench_to_zero_temperature():
     assert np.all(dE > 0) and np.all(np.diff(dE) < 0)  # above E_th and relaxing towards it
     assert np.all(np.diff(alpha) < 0)  # the effective exponent falls monotonically ...
     assert abs(alpha[-1] - 2.0 / 3.0) < 3e-3  # ... towards 2/3
+
+
+def test_p2_solve_against_the_closed_form_at_T0():
+    """End to end on the theta grid: the pure p=2 model quenched to T=0, solved
+    adaptively to t=8 (eps=1e-9, L=256), against its closed form: E at every
+    stored slice, C and R along the last slice (measured 1.7e-10, 1.6e-10 and
+    2.8e-8)."""
+    import p2_exact as px
+    p = pk.make_params({2: 1.0}, 0.0, t_max=1e3, L=256, M_cap=4096, eps=1e-9, dt0=1e-3, dt_min=1e-12)
+    s = pk.Solver(p)
+    st, info = s.step(8.0)
+    t, E = s.read(pk.F_T_GRID), s.read(pk.F_ENERGY)
+    C, R, th = s.read(pk.F_C)[-1], s.read(pk.F_R)[-1], s.read(pk.F_THETA)
+    s.close()
+    tl = t[-1]
+    eE = np.abs(E - px.E0(t)).max()
+    eC = np.abs(C - px.C0(tl, th * tl)).max()
+    eR = np.abs(R[:-1] - px.R0(tl, th[:-1] * tl)).max()
+    say(f"p=2, T=0: {info.accepted} steps to t={tl:.4g}; max error E {eE:.2e}, C {eC:.2e}, R {eR:.2e}")
+    assert eE <= 2e-9 and eC <= 2e-9 and eR <= 3e-7
+
+
+def test_p2_solve_against_the_exact_energy_at_T05():
+    """The same at T=0.5 (to t=4, L=128), where the exact solution comes from its
+    Volterra equation on a 2e-3 grid with Richardson extrapolation: the energy at
+    every stored slice against a cubic spline through the exact nodal energies
+    (measured 1e-8 at L=96 with the oracle)."""
+    import p2_exact as px
+    from scipy.interpolate import CubicSpline
+    T, tend = 0.5, 4.0
+    ex = px.WarmP2(T, tend + 0.5)
+    nodes = np.arange(ex.s.size) * ex.delta
+    spl = CubicSpline(nodes, np.array([ex.E(x) for x in nodes]))
+    p = pk.make_params({2: 1.0}, T, t_max=1e3, L=128, M_cap=4096, eps=1e-9, dt0=1e-3, dt_min=1e-12)
+    s = pk.Solver(p)
+    st, info = s.step(tend)
+    t, E = s.read(pk.F_T_GRID), s.read(pk.F_ENERGY)
+    s.close()
+    err = np.abs(E - spl(t)).max()
+    say(f"p=2, T=0.5: {info.accepted} steps to t={t[-1]:.4g}; max energy error {err:.2e}")
+    assert err <= 1e-7
+
+
+def test_fdt_approached_above_the_dynamical_transition():
+    """The 3+4 model at T=0.6, above its dynamical transition, equilibrates: the
+    fluctuation-dissipation ratio X = T R(t,t') / (d C(t,t')/dt') at fixed t-t'
+    tends to 1 as t grows (measured |1-X| at t-t'=5: 0.016 at t=100, 0.0025 at
+    t=400)."""
+    p = pk.make_params({3: 0.5, 4: 0.5}, 0.6, t_max=1e4, L=512, M_cap=8192, eps=1e-8, dt0=1e-3, dt_min=1e-12)
+    s = pk.Solver(p)
+    th = s.read(pk.F_THETA)
+    dev = {}
+    for tend in (100.0, 400.0):
+        s.step(tend)
+        t = s.read(pk.F_T_GRID)[-1]
+        C, R = s.read(pk.F_C)[-1], s.read(pk.F_R)[-1]
+        tp = th * t
+        dC = np.gradient(C, tp)
+        for tau in (0.5, 1.0, 2.0, 5.0):
+            k = int(np.argmin(np.abs((t - tp) - tau)))
+            dev[tend, tau] = abs(1.0 - 0.6 * R[k] / dC[k])
+        say(f"FDT at t={t:.4g}: |1-X| at t-t' = 0.5, 1, 2, 5: "
+            + ", ".join(f"{dev[tend, tau]:.1e}" for tau in (0.5, 1.0, 2.0, 5.0)))
+    s.close()
+    assert all(dev[400.0, tau] < 5e-3 for tau in (0.5, 1.0, 2.0, 5.0))
+    assert dev[400.0, 5.0] < dev[100.0, 5.0] / 3

@@ -267,7 +267,8 @@ def stencil_sweep(pk, torch, args) -> dict:
     state (M = 2500 slices to t = 200, stage at t = 200.08; HIP events).
     Accuracy: the largest error of one right-hand side along fixed theta against
     the exact p = 2 solution at T = 0 (history and stage from its closed form, 800
-    slices to t = 8, L = 96 and 192)."""
+    slices to t = 8, L = 96 and 192), and end to end the largest energy error of
+    the p = 2 quench to T = 0 solved to t = 8 (L = 128, eps = 1e-9)."""
     import numpy as np
 
     sys.path.insert(0, os.path.join(ROOT, "tests"))
@@ -317,10 +318,17 @@ def stencil_sweep(pk, torch, args) -> dict:
             a, b = px.dR0(tp, thp * tp)
             exR = a + thp * b
             errs.append(float(max(np.abs(gC.cpu().numpy() - exC)[:-1].max(), np.abs(gR.cpu().numpy() - exR)[:-1].max())))
+        # end to end: the p = 2 quench to T = 0 solved to t = 8, energy against the closed form
+        sp = pk.Solver(pk.make_params({2: 1.0}, 0.0, t_max=1e3, L=128, M_cap=4096, eps=1e-9, dt0=1e-3,
+                                      dt_min=1e-12, s=s_, theta_interp=interp, fh_d=d, log_r=lr))
+        sp.step(8.0)
+        tt, E = sp.read(pk.F_T_GRID), sp.read(pk.F_ENERGY)
+        sp.close()
+        e2e = float(np.abs(E - px.E0(tt)).max())
         rows.append({"scheme": name, "hist_integral_avg_launch_us": ms / n * 1e3, "p2_rhs_max_error_L96": errs[0],
-                     "p2_rhs_max_error_L192": errs[1]})
+                     "p2_rhs_max_error_L192": errs[1], "p2_solve_energy_error_L128": e2e})
         log(f"stencil {name}: {ms / n * 1e3:.1f} us per launch; p=2 RHS error {errs[0]:.2e} (L=96), "
-            f"{errs[1]:.2e} (L=192)")
+            f"{errs[1]:.2e} (L=192); p=2 solve to t=8, energy error {e2e:.2e} (L=128)")
     base = rows[0]["hist_integral_avg_launch_us"]
     for r in rows:
         r["cost_vs_default"] = r["hist_integral_avg_launch_us"] / base

@@ -502,6 +502,7 @@ __device__ __forceinline__ void hist_integral_block(const StageArgs& a, int row_
 
     double S1 = 0, S2 = 0, S3 = 0, S4 = 0, S5 = 0, S6 = 0, S7 = 0, S8 = 0, S9 = 0;
     double c0C = 0.0;
+    int mprev = 0;  // FP32 history: this lane's last bracket (its targets s = phi t grow with i)
     const int i0 = cl + kColsPerWave * ph;
 #pragma unroll 1
     for (int i = i0; i < L; i += kColStride) {
@@ -570,7 +571,18 @@ __device__ __forceinline__ void hist_integral_block(const StageArgs& a, int row_
                 const HP* p1;
                 double h00, h10, h01, h11;
                 if (nb >= 2 && s <= tb) {
-                    const int m = bracket_fast(s_t, s_bk, B, b, s);
+                    int m;
+                    if constexpr (sizeof(HS) == 4) {
+                        // warm start: the bracket of the lane's previous node, or the one after it
+                        m = mprev;
+                        if (!(s_t[m] <= s && s < s_t[m + 1])) {
+                            if (m + 2 <= b && s_t[m + 1] <= s && s < s_t[m + 2]) m = m + 1;
+                            else m = bracket_fast(s_t, s_bk, B, b, s);
+                        }
+                        mprev = m;
+                    } else {
+                        m = bracket_fast(s_t, s_bk, B, b, s);
+                    }
                     const double h = s_t[m + 1] - s_t[m];
                     const double u = (s - s_t[m]) / h;
                     h00 = 2 * u * u * u - 3 * u * u + 1;

@@ -446,7 +446,7 @@ def aging_p3(pk, torch, t_end: float = 1e4, eps: float = 1e-10) -> dict:
     them.  A history that outgrows its capacity (DMFE_ERR_CAPACITY) ends the run
     early; the rows reached are reported with the reason."""
     import numpy as np
-    cap = 8192 if t_end <= 1e4 else 16384  # the sparsified history grows with t
+    cap = 8192 if t_end <= 1e4 else 32768  # the sparsified history grows with t
     p = pk.make_params({3: 1.0}, 0.0, t_max=1e7, L=1024, M_cap=cap, eps=eps, dt0=1e-3, dt_min=1e-14)
     E_th = -np.sqrt(4.0 / 3.0)
     t0 = time.perf_counter()

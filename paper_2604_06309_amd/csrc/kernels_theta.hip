@@ -395,7 +395,7 @@ __host__ __device__ inline size_t lds_bytes(int nb, int L, bool yl) {
     return lds_offset_red(nb, L, yl) + (ph > 1 ? size_t(kRowsPerBlock) * ph * 9 * 8 : 0);
 }
 
-template <int S, int PM, class HP, bool YL, int VAR>
+template <int S, int PM, class HP, bool YL, int VAR, bool TG = false>
 __device__ __forceinline__ void hist_integral_block(const StageArgs& a, int row_block) {
     constexpr bool GEN = VAR != kVarDefault;
     // All arithmetic is FP64, also on an FP32 history: values are widened as
@@ -409,12 +409,16 @@ __device__ __forceinline__ void hist_integral_block(const StageArgs& a, int row_
     extern __shared__ double smem[];
     const int nb = a.nb;
     const int b = nb - 1;
-    double* s_t = smem;
-    int* s_bk = reinterpret_cast<int*>(smem + (nb > 0 ? nb : 1));
-    for (int q = threadIdx.x; q < nb; q += blockDim.x) s_t[q] = a.thist[q];
+    // TG: more stored slices than LDS holds times for; they are read from global memory
+    const int nbl = TG ? 0 : nb;
+    double* s_tl = smem;
+    int* s_bk = reinterpret_cast<int*>(smem + (nbl > 0 ? nbl : 1));
+    if constexpr (!TG)
+        for (int q = threadIdx.x; q < nb; q += blockDim.x) s_tl[q] = a.thist[q];
+    const double* s_t = TG ? a.thist : s_tl;
     const YPoint* ysrc = a.y;
     if (YL) {
-        YPoint* s_y = reinterpret_cast<YPoint*>(reinterpret_cast<char*>(smem) + lds_offset_y(nb));
+        YPoint* s_y = reinterpret_cast<YPoint*>(reinterpret_cast<char*>(smem) + lds_offset_y(nbl));
         for (int q = threadIdx.x; q < a.L; q += blockDim.x) s_y[q] = a.y[q];
         ysrc = s_y;
     }
@@ -652,7 +656,7 @@ __device__ __forceinline__ void hist_integral_block(const StageArgs& a, int row_
     }
     bool assemble = cl == 0;
     if (kPhases > 1) {  // rows split over waves: partial sums through LDS, summed in phase order
-        double* red = reinterpret_cast<double*>(reinterpret_cast<char*>(smem) + lds_offset_red(nb, L, YL));
+        double* red = reinterpret_cast<double*>(reinterpret_cast<char*>(smem) + lds_offset_red(nbl, L, YL));
         __syncthreads();  // every wave is done with the stage slice region and the bracket tables
         if (cl == 0) {
 #pragma unroll
@@ -699,9 +703,9 @@ __device__ __forceinline__ void hist_integral_block(const StageArgs& a, int row_
 }
 
 // One instance: the stage arguments travel by value.
-template <int S, int PM, class HP, bool YL, int VAR>
+template <int S, int PM, class HP, bool YL, int VAR, bool TG = false>
 __global__ __launch_bounds__((hist_threads<HP, VAR>())) void k_hist_integral(const StageArgs a) {
-    hist_integral_block<S, PM, HP, YL, VAR>(a, blockIdx.x);
+    hist_integral_block<S, PM, HP, YL, VAR, TG>(a, blockIdx.x);
 }
 
 // Many instances in one launch (serving): block b belongs to the instance q
@@ -1018,8 +1022,26 @@ static void launch_hi_shy(const StageArgs& a, size_t lds, hipStream_t st) {
 template <int S, class HP>
 static hipError_t launch_hi_sh(const StageArgs& a, hipStream_t st) {
     const size_t with_y = lds_bytes<HP>(a.nb, a.L, true);
-    if (with_y <= max_lds()) launch_hi_shy<S, HP, true>(a, with_y, st);
-    else launch_hi_shy<S, HP, false>(a, lds_bytes<HP>(a.nb, a.L, false), st);
+    const size_t without_y = lds_bytes<HP>(a.nb, a.L, false);
+    if (with_y <= max_lds()) {
+        launch_hi_shy<S, HP, true>(a, with_y, st);
+    } else if (without_y <= max_lds()) {
+        launch_hi_shy<S, HP, false>(a, without_y, st);
+    } else {
+        // more stored slices than LDS holds times for (above ~16K): the default scheme reads them
+        // from global memory; the other schemes are limited to histories whose times fit
+        if (a.interp != DMFE_INTERP_INDEX_LAGRANGE || a.log_r) return hipErrorInvalidValue;
+        const size_t lds = lds_bytes<HP>(0, a.L, false);
+        const dim3 grid(nblk(a.L, kRowsPerBlock)), block(hist_threads<HP>());
+        if (a.m.pmax <= 4) {
+            allow_lds(k_hist_integral<S, 4, HP, false, kVarDefault, true>, lds);
+            hipLaunchKernelGGL((k_hist_integral<S, 4, HP, false, kVarDefault, true>), grid, block, lds, st, a);
+        } else {
+            allow_lds(k_hist_integral<S, DMFE_MAX_P, HP, false, kVarDefault, true>, lds);
+            hipLaunchKernelGGL((k_hist_integral<S, DMFE_MAX_P, HP, false, kVarDefault, true>), grid, block, lds, st,
+                               a);
+        }
+    }
     return hipGetLastError();
 }
 template <int S>

@@ -348,7 +348,8 @@ dmfe_status dmfe_pool_submit(dmfe_pool* P, const dmfe_params* p, uint64_t* id) {
     const dmfe_status st = dmfe_footprint(p, &bytes);
     if (st != DMFE_OK) return st;
     // the batched kernel serves the default stencil
-    if ((p->s != 0 && p->s != 10) || p->theta_interp != DMFE_INTERP_INDEX_LAGRANGE || p->log_r != 0)
+    if ((p->s != 0 && p->s != 10) || p->theta_interp != DMFE_INTERP_INDEX_LAGRANGE || p->log_r != 0 ||
+        (p->M_cap == 0 ? p->L : p->M_cap) > 16384)
         return DMFE_ERR_UNSUPPORTED;
     if (bytes > P->arena_bytes) return DMFE_ERR_NOMEM;
     // one pool serves one history precision (the batched kernel is instantiated per precision)

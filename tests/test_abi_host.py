@@ -102,6 +102,12 @@ def test_grid_rejects_bad_params(lib):
     p.log_r = 2
     with pytest.raises(pk.DmfeError):
         pk.dmfe_grid(p)
+    # history capacity: up to 65536 slices with the default stencil, 16384 with the other schemes
+    pk.dmfe_grid(pk.make_params({3: 1.0}, 0.5, L=64, M_cap=65536))
+    for kw in (dict(M_cap=65537), dict(M_cap=16385, theta_interp=pk.INTERP_INDEX_FH), dict(M_cap=16385, log_r=True)):
+        with pytest.raises(pk.DmfeError) as e:
+            pk.dmfe_grid(pk.make_params({3: 1.0}, 0.5, L=64, **kw))
+        assert e.value.status == pk.ERR_INVALID, kw
     for kw in (dict(s=16), dict(theta_interp=pk.INTERP_THETA_FH, s=14, fh_d=13), dict(log_r=True),
                dict(theta_interp=pk.INTERP_INDEX_LAGRANGE, fh_d=99)):  # fh_d is read by the FH schemes only
         pk.dmfe_grid(pk.make_params({3: 1.0}, 0.5, L=64, **kw))

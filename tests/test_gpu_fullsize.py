@@ -71,3 +71,34 @@ def test_rhs_sampled_rows_full_size(L, M, nb_off, precision, bar, t_last, t):
         assert err <= bar * scale
         assert abs(d - o[L - 1]) <= bar * scale
         assert g[L - 1] == 0.0  # the diagonal row is pinned in the product's output
+
+
+@pytest.mark.parametrize("precision,bar,nb_off", [(pk.FP64, 1e-12, 0), (pk.FP64, 1e-12, 1), (pk.FP32_COMP, 2e-6, 0)])
+def test_rhs_with_more_slices_than_lds_holds_times_for(precision, bar, nb_off):
+    """20000 stored slices: their times no longer fit in LDS beside the kernel's other tables, and
+    the history-integral kernel reads them from global memory.  Every row against the oracle.
+    (t_max = 1e4 keeps the 64-point quadrature well conditioned: at t_max = 1e7 its weights
+    oscillate and two independent spline solves differ by ~1e-6.)"""
+    L, M, t_last, t = 64, 20000, 50.0, 50.01
+    say(f"rhs with M={M} slices (times in global memory), precision={precision}, nb=M-{nb_off}")
+    terms, T = {3: 0.5, 4: 0.5}, 0.55
+    ts = oracle.ThetaSetup(L, 1e4)
+    times = inputs.geometric_times(M, t_last, t_first=1e-4)
+    C, R, dC, dR = inputs.smooth_history(ts.th, times, 77)
+    yC, yR = inputs.smooth_stage(ts.th, t, 77)
+    if nb_off:
+        dC[-1] = 0.0
+        dR[-1] = 0.0
+    nb = M - nb_off
+    s = pk.Solver(pk.make_params(terms, T, t_max=1e4, L=L, M_cap=M + 8, eps=1e-8, precision=precision))
+    s.set_history(times, C, R, dC, dR, nb=M - 1 if nb_off else M)
+    gC, gR, gmu, gdiag = s.rhs(t, torch.tensor(yC, device="cuda"), torch.tensor(yR, device="cuda"), nb)
+    gC, gR = gC.cpu().numpy(), gR.cpu().numpy()
+    s.close()
+    oC, oR, omu, _ = oracle.theta_rhs(oracle.make_model(terms, T=T), ts, times, C, R, dC, dR, nb, t, yC, yR)
+    assert abs(gmu - omu) <= 1e-13 * max(1.0, abs(omu))
+    for g, o, d in ((gC, oC, gdiag[0]), (gR, oR, gdiag[1])):
+        scale = abs(omu) + T + np.max(np.abs(o))
+        err = np.max(np.abs(g[:-1] - o[:-1]))
+        say(f"  max error {err:.2e} (scale {scale:.3g})")
+        assert err <= bar * scale and abs(d - o[-1]) <= bar * scale

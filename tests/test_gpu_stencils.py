@@ -174,12 +174,13 @@ def test_scheme_adaptive_parity(scheme):
 
 
 def test_pool_admits_the_default_stencil_only():
-    say("pool: non-default stencils refused")
+    """The batched kernel serves the default stencil with at most 16384 stored slices."""
+    say("pool: non-default stencils and larger histories refused")
     base = dict(t_max=1e4, L=64, M_cap=100, eps=1e-8)
     pool = pk.Pool(4 * pk.dmfe_footprint(pk.make_params({3: 1.0}, 0.5, **base)), max_instances=4)
-    for kw in (dict(theta_interp=pk.INTERP_THETA_FH), dict(log_r=True), dict(s=12)):
+    for kw in (dict(theta_interp=pk.INTERP_THETA_FH), dict(log_r=True), dict(s=12), dict(M_cap=20000)):
         with pytest.raises(pk.DmfeError) as e:
-            pool.submit(pk.make_params({3: 1.0}, 0.5, **base, **kw))
+            pool.submit(pk.make_params({3: 1.0}, 0.5, **{**base, **kw}))
         assert e.value.status == pk.ERR_UNSUPPORTED, kw
     pool.submit(pk.make_params({3: 1.0}, 0.5, **base))
     pool.close()

@@ -989,28 +989,34 @@ static void allow_lds(K kernel, size_t bytes) {
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
 }
 
-template <int S, class HP, bool YL, int VAR>
+template <int S, class HP, bool YL, int VAR, bool TG = false>
 static void launch_gen(const StageArgs& a, dim3 grid, hipStream_t st) {
-    const size_t lds = lds_bytes<HP, VAR>(a.nb, a.L, YL);
-    allow_lds(k_hist_integral<S, DMFE_MAX_P, HP, YL, VAR>, lds);
-    hipLaunchKernelGGL((k_hist_integral<S, DMFE_MAX_P, HP, YL, VAR>), grid, dim3(hist_threads<HP, VAR>()), lds, st, a);
+    const size_t lds = lds_bytes<HP, VAR>(TG ? 0 : a.nb, a.L, YL);
+    allow_lds(k_hist_integral<S, DMFE_MAX_P, HP, YL, VAR, TG>, lds);
+    hipLaunchKernelGGL((k_hist_integral<S, DMFE_MAX_P, HP, YL, VAR, TG>), grid, dim3(hist_threads<HP, VAR>()), lds,
+                       st, a);
+}
+// the option schemes (theta stencils, Floater-Hormann, log-R), one instantiation each
+template <int S, class HP, bool YL, bool TG>
+static void launch_gen_var(const StageArgs& a, dim3 grid, hipStream_t st) {
+    const bool fh = a.interp == DMFE_INTERP_INDEX_FH;
+    const bool th = a.interp == DMFE_INTERP_THETA_LAGRANGE || a.interp == DMFE_INTERP_THETA_FH;
+    if (!a.log_r) {
+        if (fh) launch_gen<S, HP, YL, kVarIndexFH, TG>(a, grid, st);
+        else launch_gen<S, HP, YL, kVarTheta, TG>(a, grid, st);
+    } else if (fh) {
+        launch_gen<S, HP, YL, kVarIndexFHLog, TG>(a, grid, st);
+    } else if (th) {
+        launch_gen<S, HP, YL, kVarThetaLog, TG>(a, grid, st);
+    } else {
+        launch_gen<S, HP, YL, kVarIndexLagrangeLog, TG>(a, grid, st);
+    }
 }
 template <int S, class HP, bool YL>
 static void launch_hi_shy(const StageArgs& a, size_t lds, hipStream_t st) {
     const dim3 grid(nblk(a.L, kRowsPerBlock)), block(hist_threads<HP>());
     if (a.interp != DMFE_INTERP_INDEX_LAGRANGE || a.log_r) {
-        const bool fh = a.interp == DMFE_INTERP_INDEX_FH;
-        const bool th = a.interp == DMFE_INTERP_THETA_LAGRANGE || a.interp == DMFE_INTERP_THETA_FH;
-        if (!a.log_r) {
-            if (fh) launch_gen<S, HP, YL, kVarIndexFH>(a, grid, st);
-            else launch_gen<S, HP, YL, kVarTheta>(a, grid, st);
-        } else if (fh) {
-            launch_gen<S, HP, YL, kVarIndexFHLog>(a, grid, st);
-        } else if (th) {
-            launch_gen<S, HP, YL, kVarThetaLog>(a, grid, st);
-        } else {
-            launch_gen<S, HP, YL, kVarIndexLagrangeLog>(a, grid, st);
-        }
+        launch_gen_var<S, HP, YL, false>(a, grid, st);
     } else if (a.m.pmax <= 4) {
         allow_lds(k_hist_integral<S, 4, HP, YL, kVarDefault>, lds);
         hipLaunchKernelGGL((k_hist_integral<S, 4, HP, YL, kVarDefault>), grid, block, lds, st, a);
@@ -1028,12 +1034,12 @@ static hipError_t launch_hi_sh(const StageArgs& a, hipStream_t st) {
     } else if (without_y <= max_lds()) {
         launch_hi_shy<S, HP, false>(a, without_y, st);
     } else {
-        // more stored slices than LDS holds times for (above ~16K): the default scheme reads them
-        // from global memory; the other schemes are limited to histories whose times fit
-        if (a.interp != DMFE_INTERP_INDEX_LAGRANGE || a.log_r) return hipErrorInvalidValue;
+        // more stored slices than LDS holds times for (above ~16K): they are read from global memory
         const size_t lds = lds_bytes<HP>(0, a.L, false);
         const dim3 grid(nblk(a.L, kRowsPerBlock)), block(hist_threads<HP>());
-        if (a.m.pmax <= 4) {
+        if (a.interp != DMFE_INTERP_INDEX_LAGRANGE || a.log_r) {
+            launch_gen_var<S, HP, false, true>(a, grid, st);
+        } else if (a.m.pmax <= 4) {
             allow_lds(k_hist_integral<S, 4, HP, false, kVarDefault, true>, lds);
             hipLaunchKernelGGL((k_hist_integral<S, 4, HP, false, kVarDefault, true>), grid, block, lds, st, a);
         } else {

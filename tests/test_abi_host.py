@@ -102,9 +102,11 @@ def test_grid_rejects_bad_params(lib):
     p.log_r = 2
     with pytest.raises(pk.DmfeError):
         pk.dmfe_grid(p)
-    # history capacity: up to 65536 slices with the default stencil, 16384 with the other schemes
-    pk.dmfe_grid(pk.make_params({3: 1.0}, 0.5, L=64, M_cap=65536))
-    for kw in (dict(M_cap=65537), dict(M_cap=16385, theta_interp=pk.INTERP_INDEX_FH), dict(M_cap=16385, log_r=True)):
+    # history capacity: up to 65536 slices with every scheme
+    for kw in (dict(), dict(theta_interp=pk.INTERP_INDEX_FH), dict(theta_interp=pk.INTERP_THETA_LAGRANGE),
+               dict(log_r=True)):
+        pk.dmfe_grid(pk.make_params({3: 1.0}, 0.5, L=64, M_cap=65536, **kw))
+    for kw in (dict(M_cap=65537), dict(M_cap=65537, theta_interp=pk.INTERP_INDEX_FH), dict(M_cap=15)):
         with pytest.raises(pk.DmfeError) as e:
             pk.dmfe_grid(pk.make_params({3: 1.0}, 0.5, L=64, **kw))
         assert e.value.status == pk.ERR_INVALID, kw

@@ -101,6 +101,22 @@ def test_scheme_rhs_parity(scheme, L, M, nb, t, seed, hist):
     _check(gC, gR, gdiag, oC, oR, gmu, omu, 1e-12)
 
 
+@pytest.mark.parametrize("scheme", SCHEMES, ids=IDS)
+@pytest.mark.parametrize("nb_off,precision,bar", [(0, pk.FP64, 1e-12), (1, pk.FP64, 1e-12),
+                                                  (0, pk.FP32_COMP, 2e-6)])
+def test_scheme_more_slices_than_lds_holds_times_for(scheme, nb_off, precision, bar):
+    """20000 stored slices: beyond the ~16K slice times that LDS holds, the history-integral kernel
+    of every scheme reads them from global memory.  R changes sign, so the log-R schemes take both
+    the log branch and the fallback.  Every row against the oracle."""
+    interp, d, log_r = scheme
+    L, M = 64, 20000
+    say(f"scheme rhs with M={M} slices (times in global memory) interp={interp} d={d} log_r={log_r} "
+        f"nb=M-{nb_off} precision={precision}")
+    gC, gR, gmu, gdiag, oC, oR, omu = _rhs(L, M, M - nb_off, 50.0, 21, interp, d, log_r, precision=precision,
+                                           hist="sign")
+    _check(gC, gR, gdiag, oC, oR, gmu, omu, bar)
+
+
 @pytest.mark.parametrize("interp,s,d,log_r", [
     (pk.INTERP_INDEX_LAGRANGE, 16, 0, False),   # the default scheme on the largest stencil
     (pk.INTERP_THETA_FH, 14, 9, False),         # a wider Floater-Hormann stencil of degree 9

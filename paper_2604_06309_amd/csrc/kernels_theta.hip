@@ -1034,7 +1034,8 @@ static hipError_t launch_hi_sh(const StageArgs& a, hipStream_t st) {
     } else if (without_y <= max_lds()) {
         launch_hi_shy<S, HP, false>(a, without_y, st);
     } else {
-        // more stored slices than LDS holds times for (above ~16K): they are read from global memory
+        // more stored slices than LDS holds times for (about 19K with 160 KB of LDS): they are read from
+        // global memory
         const size_t lds = lds_bytes<HP>(0, a.L, false);
         const dim3 grid(nblk(a.L, kRowsPerBlock)), block(hist_threads<HP>());
         if (a.interp != DMFE_INTERP_INDEX_LAGRANGE || a.log_r) {

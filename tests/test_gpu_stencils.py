@@ -105,7 +105,7 @@ def test_scheme_rhs_parity(scheme, L, M, nb, t, seed, hist):
 @pytest.mark.parametrize("nb_off,precision,bar", [(0, pk.FP64, 1e-12), (1, pk.FP64, 1e-12),
                                                   (0, pk.FP32_COMP, 2e-6)])
 def test_scheme_more_slices_than_lds_holds_times_for(scheme, nb_off, precision, bar):
-    """20000 stored slices: beyond the ~16K slice times that LDS holds, the history-integral kernel
+    """20000 stored slices: beyond the ~19K slice times that LDS holds, the history-integral kernel
     of every scheme reads them from global memory.  R changes sign, so the log-R schemes take both
     the log branch and the fallback.  Every row against the oracle."""
     interp, d, log_r = scheme

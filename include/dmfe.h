@@ -160,7 +160,8 @@ typedef struct dmfe_step_info {
     int64_t rhs_evals;      /* right-hand-side evaluations (stages) */
     int64_t M;              /* stored slices (uniform mode: stored rows) */
     int32_t scheme;         /* DMFE_SCHEME_* in use */
-    int32_t reserved0;
+    int32_t nb_valid;       /* leading stored slices that carry their d/dt (M, or M-1 when the newest
+                               slice's derivative is formed at the next step's first stage) */
     double t;               /* current time */
     double dt;              /* next step size */
     double eps_rk;          /* error estimate of the last step */
@@ -180,7 +181,14 @@ typedef enum dmfe_field {
     DMFE_F_MU = 9       /* mu(t_n), [count]                                                */
 } dmfe_field;
 
-/* Bytes of device memory the handle needs for these parameters (host only, no device call). */
+/*
+ * Bytes of device memory the handle needs for these parameters (host only, no
+ * device call).  Infrastructure, not a step of the method: it sizes a caller
+ * workspace and the serving pool's admission test.  The bulk is the history of
+ * Sec. 3.2 (M_cap + 1 slices of C, R and their t-derivatives: 32 bytes per
+ * point in FP64, 16 with an FP32 history) plus O(L) arrays.  Errors:
+ * DMFE_ERR_INVALID / DMFE_ERR_UNSUPPORTED as dmfe_create would return them.
+ */
 dmfe_status dmfe_footprint(const dmfe_params *params, size_t *bytes);
 
 /*
@@ -192,9 +200,20 @@ dmfe_status dmfe_create(const dmfe_params *params, const dmfe_resources *res, dm
 
 /*
  * Advance until t >= min(t_target, t_max) (uniform mode: until n h >= t_target
- * or n = N) or until max_steps steps (accepted + rejected) were taken.  Sparsification runs
- * automatically when the history reaches M_cap.  info may be NULL.
- * Returns DMFE_DONE once t >= t_max (adaptive) or n = N (uniform).
+ * or n = N) or until max_steps steps (accepted + rejected) were taken.
+ * Adaptive mode follows Sec. 3.5: each step evaluates the right-hand side of
+ * Sec. 3.3-3.4 at every stage of Dormand-Prince 5(4) (SSPRK(10,4) once dt
+ * reaches DP5's real-axis stability limit), forms the 1-norm error estimate
+ * over all grid points and both fields, and accepts (dt x 0.9 when
+ * eps < err <= 2 eps, x 1.01 when err < eps/2) or rejects (err > 2 eps: the
+ * last min(10, M-1) slices are dropped and dt halved).  An accepted step
+ * appends the new slice to the history (Sec. 3.2).  Sparsification (Sec. 3.6,
+ * as dmfe_sparsify) runs automatically when the history reaches M_cap.
+ * Uniform mode: classical RK4 steps of the trapezoid scheme of Sec. 2.3.
+ * info (host, may be NULL) receives the counters and state.
+ * Returns DMFE_OK, DMFE_DONE once t >= t_max (adaptive) or n = N (uniform),
+ * DMFE_ERR_CAPACITY, DMFE_ERR_STEP_UNDERFLOW (dt < dt_min), DMFE_ERR_NONFINITE
+ * or DMFE_ERR_DEVICE; on an error the handle keeps the last accepted state.
  */
 dmfe_status dmfe_step(dmfe_handle *h, double t_target, int64_t max_steps, dmfe_step_info *info);
 
@@ -210,9 +229,13 @@ dmfe_status dmfe_sparsify(dmfe_handle *h, int32_t passes, int64_t *removed);
 
 /*
  * Copy `count` entries starting at `first` of a field into dst (device memory
- * if dst_on_device, else host).  With dst == NULL only *needed_bytes is set.
+ * if dst_on_device, else host; caller-owned, dst_bytes long).  Infrastructure,
+ * not a step of the method: it exposes the stored history of Sec. 3.2 (t_n,
+ * C, R and their t-derivatives, in logical slice order, as FP64 whatever the
+ * storage precision) and the observables E(t_n), mu(t_n) of Sec. 2.1 formed
+ * from the stored slices.  With dst == NULL only *needed_bytes is set.
  * Returns DMFE_ERR_BUFFER if dst_bytes is too small, DMFE_ERR_INVALID if the
- * range is outside the stored data.
+ * range is outside the stored data.  Synchronises the handle's stream.
  */
 dmfe_status dmfe_read(dmfe_handle *h, int32_t field, int64_t first, int64_t count, void *dst, size_t dst_bytes,
                       int32_t dst_on_device, size_t *needed_bytes);

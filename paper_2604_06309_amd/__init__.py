@@ -54,7 +54,7 @@ class dmfe_resources(ctypes.Structure):
 class dmfe_step_info(ctypes.Structure):
     _fields_ = [("accepted", ctypes.c_int64), ("rejected", ctypes.c_int64), ("reverts", ctypes.c_int64),
                 ("sparsify_calls", ctypes.c_int64), ("removed", ctypes.c_int64), ("rhs_evals", ctypes.c_int64),
-                ("M", ctypes.c_int64), ("scheme", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("M", ctypes.c_int64), ("scheme", ctypes.c_int32), ("nb_valid", ctypes.c_int32),
                 ("t", ctypes.c_double), ("dt", ctypes.c_double), ("eps_rk", ctypes.c_double)]
 
     def as_dict(self) -> dict:

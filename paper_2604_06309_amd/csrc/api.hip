@@ -363,8 +363,10 @@ dmfe_status sparsify_pass(dmfe_handle* h, int64_t* removed_out) {
             h->slot[w] = h->slot[n];
             ++w;
         }
+        // only the first M-12 slices are candidates, so the slices without a stored
+        // d/dt (at most the newest) are still the last ones
+        h->nb_valid = w - (M - h->nb_valid);
         h->M = w;
-        h->nb_valid = std::min(h->nb_valid, w);
         h->thist.resize(w);
         h->slot.resize(w);
         dmfe_status st = upload_order(h);
@@ -388,6 +390,7 @@ void fill_info(const dmfe_handle* h, dmfe_step_info* info) {
     info->rhs_evals = h->rhs_evals;
     info->scheme = h->scheme;
     info->eps_rk = h->eps_rk;
+    info->nb_valid = h->p.mode == DMFE_UNIFORM ? int32_t(h->un + 1) : h->nb_valid;
     if (h->p.mode == DMFE_UNIFORM) {
         info->M = h->un + 1;
         info->t = double(h->un) * h->p.h;

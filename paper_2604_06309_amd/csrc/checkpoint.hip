@@ -4,7 +4,7 @@
 // it returns; the file itself is written synchronously or by one background
 // thread per handle (a second save waits for the first).
 //
-// File format (version 1, host byte order):
+// File format (version 2, host byte order):
 //   CkptHeader
 //   t_n of the M stored slices               M doubles, logical order
 //   the state y(t)                           L YPoint (FP64; an FP32 history holds only its rounding)
@@ -12,7 +12,10 @@
 //   stage
 //   the M stored slices                      M x L points in the handle's storage format, logical order
 // The header records the solve's parameters, the controller state and the
-// counters, and an FNV-1a checksum over the payload (64-bit words).
+// counters, and an FNV-1a checksum (64-bit words) over the header, with its
+// checksum field zeroed, followed by the payload: an altered parameter, state
+// or counter is refused like an altered history.
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <thread>
@@ -26,7 +29,7 @@ namespace core {
 namespace {
 
 constexpr char kMagic[8] = {'D', 'M', 'F', 'E', 'C', 'K', 'P', '1'};
-constexpr uint32_t kVersion = 1;
+constexpr uint32_t kVersion = 2;
 
 struct CkptHeader {
     char magic[8];
@@ -41,8 +44,8 @@ struct CkptHeader {
     uint64_t checksum;
 };
 
-uint64_t fnv1a64(const unsigned char* p, size_t n) {
-    uint64_t h = 1469598103934665603ull;
+constexpr uint64_t kFnvBasis = 1469598103934665603ull;
+uint64_t fnv1a64(const unsigned char* p, size_t n, uint64_t h = kFnvBasis) {
     size_t q = 0;
     for (; q + 8 <= n; q += 8) {
         uint64_t w;
@@ -53,11 +56,24 @@ uint64_t fnv1a64(const unsigned char* p, size_t n) {
     return h;
 }
 
-dmfe_status write_file(const std::string& path, CkptHeader hdr, const std::vector<unsigned char>& payload) {
-    hdr.checksum = fnv1a64(payload.data(), payload.size());
+// Checksum of the header bytes as written (checksum field taken as zero) and
+// the payload.  The header is hashed from a byte copy, so padding bytes count
+// exactly as they are stored.
+uint64_t file_checksum(const unsigned char (&hb)[sizeof(CkptHeader)], const std::vector<unsigned char>& payload) {
+    unsigned char z[sizeof(CkptHeader)];
+    std::memcpy(z, hb, sizeof(z));
+    std::memset(z + offsetof(CkptHeader, checksum), 0, sizeof(uint64_t));
+    return fnv1a64(payload.data(), payload.size(), fnv1a64(z, sizeof(z)));
+}
+
+dmfe_status write_file(const std::string& path, const CkptHeader& hdr, const std::vector<unsigned char>& payload) {
+    unsigned char hb[sizeof(CkptHeader)];
+    std::memcpy(hb, &hdr, sizeof(hb));
+    const uint64_t sum = file_checksum(hb, payload);
+    std::memcpy(hb + offsetof(CkptHeader, checksum), &sum, sizeof(sum));
     FILE* f = std::fopen(path.c_str(), "wb");
     if (!f) return fail_msg(DMFE_ERR_INVALID, "checkpoint: cannot open " + path + " for writing");
-    const bool ok = std::fwrite(&hdr, sizeof(hdr), 1, f) == 1 &&
+    const bool ok = std::fwrite(hb, sizeof(hb), 1, f) == 1 &&
                     std::fwrite(payload.data(), 1, payload.size(), f) == payload.size() && std::fflush(f) == 0;
     const bool closed = std::fclose(f) == 0;
     if (!ok || !closed) return fail_msg(DMFE_ERR_INVALID, "checkpoint: write to " + path + " failed");
@@ -159,11 +175,14 @@ dmfe_status dmfe_checkpoint_load(const char* path, const dmfe_resources* res, dm
     FILE* f = std::fopen(path, "rb");
     if (!f) return fail_msg(DMFE_ERR_INVALID, std::string("checkpoint: cannot open ") + path);
     CkptHeader hdr{};
-    const bool hdr_ok = std::fread(&hdr, sizeof(hdr), 1, f) == 1 && std::memcmp(hdr.magic, kMagic, 8) == 0 &&
-                        hdr.version == kVersion && hdr.header_bytes == sizeof(CkptHeader);
+    unsigned char hb[sizeof(CkptHeader)];
+    const bool got = std::fread(hb, sizeof(hb), 1, f) == 1;
+    if (got) std::memcpy(&hdr, hb, sizeof(hb));
+    const bool hdr_ok = got && std::memcmp(hdr.magic, kMagic, 8) == 0 && hdr.version == kVersion &&
+                        hdr.header_bytes == sizeof(CkptHeader);
     if (!hdr_ok) {
         std::fclose(f);
-        return fail_msg(DMFE_ERR_INVALID, std::string("checkpoint: not a version-1 checkpoint: ") + path);
+        return fail_msg(DMFE_ERR_INVALID, std::string("checkpoint: not a version-2 checkpoint: ") + path);
     }
     const dmfe_params& p = hdr.params;
     const size_t pb = p.precision == DMFE_FP32_COMP ? sizeof(HPoint32) : sizeof(HPoint);
@@ -179,7 +198,7 @@ dmfe_status dmfe_checkpoint_load(const char* path, const dmfe_resources* res, dm
     std::vector<unsigned char> payload(hdr.payload_bytes);
     const bool read_ok = std::fread(payload.data(), 1, payload.size(), f) == payload.size();
     std::fclose(f);
-    if (!read_ok || fnv1a64(payload.data(), payload.size()) != hdr.checksum)
+    if (!read_ok || file_checksum(hb, payload) != hdr.checksum)
         return fail_msg(DMFE_ERR_INVALID, std::string("checkpoint: truncated or corrupted: ") + path);
 
     dmfe_handle* h = nullptr;

@@ -112,9 +112,6 @@ class WarmP2:
             gam[k] = (Gv[k] + 2 * T * d * acc) / (1.0 - T * d * Gv[0])
         return gam
 
-    def _int(self, fvals_fn, upto_idx_fn):
-        raise NotImplementedError
-
     def _trap(self, n, idx_t, idx_tp, deriv=False):
         """int_0^{t'} G(t+t'-2s) Gamma(s) ds on the grid with n panels over [0, tmax]."""
         gam = self._g_fine[0] if n == self.s.size - 1 else self._g_fine[1]

@@ -211,3 +211,63 @@ def test_checkpoint_load_rejects_bad_files(lib, tmp_path):
         pk.dmfe_checkpoint_load(str(junk))
     assert e.value.status == pk.ERR_INVALID
     assert "checkpoint" in pk.dmfe_last_error()
+
+
+class _CkptHeader(ctypes.Structure):
+    """The checkpoint file header (version 2) as the library writes it."""
+    _fields_ = [("magic", ctypes.c_char * 8), ("version", ctypes.c_uint32), ("header_bytes", ctypes.c_uint32),
+                ("params", pk.dmfe_params), ("M", ctypes.c_int64), ("nb_valid", ctypes.c_int64),
+                ("accepted", ctypes.c_int64), ("rejected", ctypes.c_int64), ("reverts", ctypes.c_int64),
+                ("n_sparsify", ctypes.c_int64), ("removed", ctypes.c_int64), ("rhs_evals", ctypes.c_int64),
+                ("t", ctypes.c_double), ("dt", ctypes.c_double), ("eps_rk", ctypes.c_double),
+                ("scheme", ctypes.c_int32), ("fsal_valid", ctypes.c_int32), ("point_bytes", ctypes.c_int32),
+                ("L", ctypes.c_int32), ("payload_bytes", ctypes.c_uint64), ("checksum", ctypes.c_uint64)]
+
+
+def _fnv1a64_words(data: bytes, h: int = 1469598103934665603) -> int:
+    """FNV-1a over little-endian 64-bit words, then the trailing bytes."""
+    mask = (1 << 64) - 1
+    n8 = len(data) // 8 * 8
+    for w in np.frombuffer(data[:n8], dtype="<u8").tolist():
+        h = ((h ^ w) * 1099511628211) & mask
+    for b in data[n8:]:
+        h = ((h ^ b) * 1099511628211) & mask
+    return h
+
+
+def test_checkpoint_header_is_covered_by_the_checksum(lib, tmp_path):
+    """A checkpoint file written here in the library's format (one slice, L = 32,
+    FP64) passes the load's checks and only then needs a device; the same file
+    with one bit of the temperature, of the payload or of the version changed is
+    refused with DMFE_ERR_INVALID before any device call."""
+    L, M = 32, 1
+    p = pk.make_params({3: 0.5, 4: 0.5}, 0.6, t_max=1e4, L=L, M_cap=64, eps=1e-8, dt0=1e-3, dt_min=1e-12)
+    payload = np.concatenate([np.zeros(M), np.ones(2 * L), np.zeros(2 * L), np.tile([1.0, 1.0, 0.0, 0.0], L)])
+    payload = payload.tobytes()
+    hdr = _CkptHeader()
+    hdr.magic = b"DMFECKP1"
+    hdr.version, hdr.header_bytes = 2, ctypes.sizeof(_CkptHeader)
+    hdr.params = p
+    hdr.M, hdr.nb_valid, hdr.dt, hdr.point_bytes, hdr.L = M, 0, 1e-3, 32, L
+    hdr.payload_bytes = len(payload)
+    hdr.checksum = _fnv1a64_words(payload, _fnv1a64_words(bytes(hdr)))
+    good = bytes(hdr) + payload
+
+    def load(raw: bytes) -> int:
+        path = tmp_path / "c.ckpt"
+        path.write_bytes(raw)
+        out = ctypes.c_void_p()
+        res = pk.dmfe_resources()
+        st = lib.dmfe_checkpoint_load(os.fsencode(str(path)), ctypes.byref(res), ctypes.byref(out))
+        if out.value:
+            lib.dmfe_destroy(out)
+        return st
+
+    # valid: the checks pass and loading proceeds to the device (absent on a CPU-only host)
+    assert load(good) in (pk.OK, pk.ERR_DEVICE)
+    t_at = _CkptHeader.params.offset + pk.dmfe_params.T.offset
+    for at in (t_at + 2, t_at + 7, len(good) - 3, _CkptHeader.version.offset):
+        raw = bytearray(good)
+        raw[at] ^= 0x10
+        assert load(bytes(raw)) == pk.ERR_INVALID, at
+    assert load(good[:-1]) == pk.ERR_INVALID

@@ -67,12 +67,39 @@ def test_corrupted_checkpoint_is_refused(tmp_path):
     s.step(float("inf"), 40)
     s.checkpoint(str(path))
     s.close()
-    raw = bytearray(path.read_bytes())
-    raw[-9] ^= 0x40  # one bit of the stored history
-    path.write_bytes(bytes(raw))
-    with pytest.raises(pk.DmfeError) as e:
-        pk.Solver.load(str(path), p)
-    assert e.value.status == pk.ERR_INVALID
+    good = path.read_bytes()
+    # one bit of the stored history; one bit of the temperature in the header's parameters
+    # (the header starts with an 8-byte magic and two 32-bit words, then the dmfe_params)
+    for at in (len(good) - 9, 16 + pk.dmfe_params.T.offset + 3):
+        raw = bytearray(good)
+        raw[at] ^= 0x40
+        path.write_bytes(bytes(raw))
+        with pytest.raises(pk.DmfeError) as e:
+            pk.Solver.load(str(path), p)
+        assert e.value.status == pk.ERR_INVALID
+    path.write_bytes(good)
+    pk.Solver.load(str(path), p).close()
+
+
+def test_sparsify_keeps_the_newest_slice_without_derivative():
+    """A history whose newest slice has no stored d/dt yet (nb = M-1): a
+    sparsification pass removes older slices only (candidates 1..M-12), so the
+    newest slice is still the one without a derivative afterwards."""
+    L, M = 64, 60
+    p = pk.make_params({3: 0.5, 4: 0.5}, 0.6, t_max=1e4, L=L, M_cap=100, eps=1e-8)
+    s = pk.Solver(p)
+    th = s.read(pk.F_THETA)
+    times = 0.1 * np.arange(M)
+    # linear in t along fixed theta, with its exact derivative: every residual vanishes
+    C = np.array([1.0 - 0.01 * (1 - th) * t for t in times])
+    dC = np.array([-0.01 * (1 - th) for _ in times])
+    s.set_history(times, C, C, dC, dC, nb=M - 1)
+    assert s.info().nb_valid == M - 1
+    removed = s.sparsify(1)
+    info = s.info()
+    s.close()
+    assert removed > 0 and info.M == M - removed
+    assert info.nb_valid == info.M - 1
 
 
 def test_parameter_record(tmp_path):

@@ -404,3 +404,160 @@ def test_adaptive_p2_energy_against_exact():
     assert err.max() < 2e-6
     # the diagonal stays pinned and the state is finite
     assert np.all(C[:, -1] == 1.0) and np.all(np.isfinite(C))
+
+
+# ----------------------------------------------------------------------------- theta grid: equilibrium start
+def _equilibrium_run(L):
+    """Pure p = 3 (f = q^3/2) at T = 1 > T_d = 0.6124 started in equilibrium
+    (beta0 = 1/T, Sec. 2.1 forcing term), solved on the theta grid to t = 6."""
+    T = 1.0
+    m = oracle.make_model({3: 1.0}, T=T, beta0=1.0 / T)
+    ts = oracle.ThetaSetup(L, 1e4)
+    run = oracle.AdaptiveRun(m, ts, eps=1e-8, dt0=1e-3, dt_min=1e-12, M_cap=4000)
+    assert run.run(6.0, 100000) == 1
+    return m, ts, run
+
+
+def test_theta_equilibrium_start_is_stationary():
+    """An equilibrium start stays in equilibrium (derived from Sec. 2.1 with
+    beta0 = 1/T): E(t) = -f(1)/T and mu(t) = T + f'(1)/T at every stored slice,
+    C(t, t - tau) independent of t, and the FDT R(tau) = -C'(tau)/T.  All four
+    hold up to the discretisation error, which falls as L grows.  The forcing
+    term F_C = beta0 f'(C(t,0)) C(t',0) enters only at t > 0, so this is the pin
+    that tells C(t,0) from C(t',0)."""
+    errs = []
+    for L in (48, 96):
+        m, ts, run = _equilibrium_run(L)
+        t, C, R, dC, dR = run.history()
+        mE = np.array([oracle.mu_energy(m, ts, tt, C[i], R[i]) for i, tt in enumerate(t)])
+        eE = np.abs(mE[:, 1] + oracle.f(m, 1.0) / m.T).max()
+        eM = np.abs(mE[:, 0] - m.T - oracle.f1(m, 1.0) / m.T).max()
+        # stationarity: C and R at fixed tau = t - t' on every slice with t >= tau + 1/4
+        eS = 0.0
+        for tau in (0.5, 1.0, 2.0):
+            vals = []
+            for n in range(run.M):
+                if t[n] < tau + 0.25:
+                    continue
+                thc = tau / t[n]
+                x = oracle.index_of(L, 1e4, 1.0 - thc, thc)
+                vals.append(oracle.hist_value(ts, t, C, R, dC, dR, run.M, t[-1], C[-1], R[-1], t[n], -1, x,
+                                              1.0 - thc, thc))
+            vals = np.array(vals)
+            eS = max(eS, np.ptp(vals[:, 0]), np.ptp(vals[:, 1]))
+        # FDT on the slice before the last (its stored d/dt along fixed theta is
+        # C'(tau) (1 - theta) in equilibrium): R = -dC / ((1 - theta) T)
+        n = run.M - 2
+        tau = ts.thc * t[n]
+        sel = (tau > 0.2) & (tau < 4.0)
+        eF = np.abs(R[n, sel] + dC[n, sel] / (ts.thc[sel] * m.T)).max()
+        errs.append((eE, eM, eS, eF))
+    (e48, e96) = errs
+    assert e96[0] < 3e-7 and e96[1] < 1e-6 and e96[2] < 3e-6 and e96[3] < 3e-5
+    for a, b in zip(e48, e96):
+        assert b < a / 8
+
+
+# ----------------------------------------------------------------------------- sparsification pass
+def _load_history(run, t, C, R, dC, dR):
+    M = t.size
+    run.t[:M], run.C[:M], run.R[:M], run.dC[:M], run.dR[:M] = t, C, R, dC, dR
+    run.st.M = M
+
+
+def test_sparsify_pass_range_threshold_and_compaction():
+    """One pass of Sec. 3.6 through the oracle's driver state: candidates are
+    n = 1..M-12 (the first slice and the revert window of the last eleven are
+    kept), a slice goes when its residual is below eps/10 and the next candidate
+    is then skipped, and the kept slices are compacted in order.
+
+    History quartic in t on a uniform grid: every residual equals the closed
+    form 1.5 L |H[a,b] + H[b,c] - H[a,c]| of the Hermite integrals of t^4 (C
+    = t^4 and R = C/2 at each of the L nodes), so a threshold 1% above it drops exactly 1, 3, ..., 17 of
+    M = 30 slices and one 1% below drops none; a cubic history drops the same
+    slices at any tolerance."""
+    L, M = 16, 30
+    m = oracle.make_model({2: 1.0}, T=0.0)
+    ts = oracle.ThetaSetup(L, 1e3)
+    times = 0.3 * np.arange(M)
+    one = np.ones(L)
+    C = np.array([tt ** 4 * one for tt in times])
+    dC = np.array([4 * tt ** 3 * one for tt in times])
+    hi = lambda x, y: (y - x) * (x ** 4 + y ** 4) / 2 + (y - x) ** 2 * (4 * x ** 3 - 4 * y ** 3) / 12
+    res = 1.5 * L * abs(hi(times[0], times[1]) + hi(times[1], times[2]) - hi(times[0], times[2]))
+    assert res > 0
+    kept = [n for n in range(M) if not (n % 2 == 1 and n <= 17)]
+    for factor, expect in ((1.01, kept), (0.99, list(range(M)))):
+        run = oracle.AdaptiveRun(m, ts, eps=10.0 * res * factor, dt0=1e-3, dt_min=1e-12, M_cap=64)
+        _load_history(run, times, C, 0.5 * C, dC, 0.5 * dC)
+        removed = run.sparsify(1)
+        assert removed == M - len(expect)
+        assert run.M == len(expect) and run.st.removed == removed and run.st.n_sparsify == 1
+        t2, C2, R2, dC2, dR2 = run.history()
+        assert np.array_equal(t2, times[expect])
+        assert np.array_equal(C2, C[expect]) and np.array_equal(dR2, 0.5 * dC[expect])
+    # cubic history: zero residual everywhere, the same greedy selection
+    rng = np.random.default_rng(11)
+    cf = rng.normal(size=(4, L))
+    tt = np.cumsum(rng.uniform(0.1, 0.4, M))
+    C3 = np.array([cf[0] + cf[1] * x + cf[2] * x ** 2 + cf[3] * x ** 3 for x in tt])
+    dC3 = np.array([cf[1] + 2 * cf[2] * x + 3 * cf[3] * x ** 2 for x in tt])
+    run = oracle.AdaptiveRun(m, ts, eps=1e-9, dt0=1e-3, dt_min=1e-12, M_cap=64)
+    _load_history(run, tt, C3, C3, dC3, dC3)
+    assert run.sparsify(1) == 9
+    assert np.array_equal(run.history()[0], tt[kept])
+    # a short history has no candidates
+    run = oracle.AdaptiveRun(m, ts, eps=1.0, dt0=1e-3, dt_min=1e-12, M_cap=64)
+    _load_history(run, tt[:12], C3[:12], C3[:12], dC3[:12], dC3[:12])
+    assert run.sparsify(1) == 0 and run.M == 12
+
+
+# ----------------------------------------------------------------------------- controller: reject and revert
+def _scripted_state(M):
+    """A p = 2 history of M slices from the oracle's own driver (loose tolerance,
+    every step accepted), then a step of dt = 0.5 from it."""
+    m = oracle.make_model({2: 1.0}, T=0.0)
+    ts = oracle.ThetaSetup(32, 1e3)
+    run = oracle.AdaptiveRun(m, ts, eps=1e3, dt0=0.05, dt_min=1e-12, M_cap=64)
+    run.run(1e9, M - 1)
+    assert run.M == M and run.st.rejected == 0
+    return m, ts, run.history()
+
+
+def _step_once(m, ts, hist, eps, dt):
+    t, C, R, dC, dR = hist
+    run = oracle.AdaptiveRun(m, ts, eps=eps, dt0=dt, dt_min=1e-12, M_cap=64)
+    _load_history(run, t, C, R, dC, dR)
+    run.st.dt = dt
+    run.run(1e9, 1)
+    return run
+
+
+@pytest.mark.parametrize("M", [15, 5])
+def test_controller_bands_and_revert(M):
+    """Sec. 3.5 on one scripted step whose error estimate eps_RK is fixed by the
+    state and dt alone (not by the tolerance): eps_RK > 2 eps rejects, drops the
+    last min(10, M-1) slices, halves dt and leaves the kept slices untouched;
+    eps < eps_RK <= 2 eps accepts with dt x 0.9; eps/2 <= eps_RK <= eps accepts
+    with dt unchanged; eps_RK < eps/2 accepts with dt x 1.01."""
+    m, ts, hist = _scripted_state(M)
+    dt = 0.5  # DP5 boundary at dt 4 = 3.3065 is not reached by 1.01 dt
+    probe = _step_once(m, ts, hist, 1e3, dt)
+    e_rk = probe.st.last_eps
+    assert e_rk > 0 and probe.st.accepted == 1 and probe.M == M + 1
+    nrev = min(10, M - 1)
+    run = _step_once(m, ts, hist, e_rk / 3.0, dt)
+    assert run.st.last_eps == e_rk
+    assert run.st.rejected == 1 and run.M == M - nrev and run.st.dt == 0.5 * dt
+    t2, C2, R2, dC2, dR2 = run.history()
+    k = M - nrev
+    assert np.array_equal(t2, hist[0][:k]) and np.array_equal(C2, hist[1][:k]) and np.array_equal(R2, hist[2][:k])
+    assert np.array_equal(dC2[: k - 1], hist[3][: k - 1]) and np.array_equal(dR2[: k - 1], hist[4][: k - 1])
+    for eps, factor in ((e_rk / 1.5, 0.9), (e_rk / 0.8, 1.0), (e_rk * 3.0, 1.01)):
+        run = _step_once(m, ts, hist, eps, dt)
+        assert run.st.rejected == 0 and run.M == M + 1 and run.st.scheme == 0
+        assert run.st.dt == factor * dt if factor != 1.0 else run.st.dt == dt
+        assert run.t[M] == hist[0][-1] + dt
+    # the band edge 2 eps itself is accepted
+    run = _step_once(m, ts, hist, e_rk / 2.0, dt)
+    assert run.st.rejected == 0 and run.st.dt == 0.9 * dt

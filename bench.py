@@ -251,6 +251,44 @@ def kernel_bench(pk, args) -> dict:
             "achieved_GBps": alg / (avg_us * 1e-6) / 1e9, "calibration_copies": cal}
 
 
+def sparsify_bench(pk, torch, L: int = 4096, M: int = 4096, reps: int = 10) -> dict:
+    """The sparsification residual kernel (Sec. 3.6) alone: one pass over a full
+    history of M slices at L = 4096 (the workload's capacity): seeded uniform
+    random values at geometrically spaced times, whose residuals are far above
+    the tiny tolerance used, so no slice is removed and every pass sees the
+    same M - 12 candidates (the kernel's cost does not depend on the values).
+    Algorithmic bytes: the four FP64 (or FP32) fields of every stored point
+    read once."""
+    import numpy as np
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import inputs
+    out = {}
+    for name, prec in (("fp64", pk.FP64), ("fp32c", pk.FP32_COMP)):
+        s = pk.Solver(pk.make_params({3: 0.5, 4: 0.5}, 0.55, t_max=1e7, L=L, M_cap=M, eps=1e-300, dt0=1e-3,
+                                     dt_min=1e-310, precision=prec))
+        th = s.read(pk.F_THETA)
+        times = inputs.geometric_times(M, 200.0, t_first=0.01)
+        rng = np.random.default_rng(20260406)
+        C, R = rng.uniform(0.0, 1.0, (2, M, L))
+        dC, dR = rng.uniform(-1.0, 1.0, (2, M, L))
+        s.set_history(times, C, R, dC, dR)
+        del C, R, dC, dR
+        s.sparsify(1)
+        s.timing(True)
+        for _ in range(reps):
+            assert s.sparsify(1) == 0
+        torch.cuda.synchronize()
+        n, ms, _ = s.timing_read(pk.K_SPARSIFY)
+        s.timing(False)
+        s.close()
+        us = ms / n * 1e3
+        alg = M * L * (32.0 if prec == pk.FP64 else 16.0)
+        out[name] = {"avg_pass_us": us, "algorithmic_bytes_per_pass": alg, "achieved_GBps": alg / (us * 1e-6) / 1e9,
+                     "frac_of_hbm_peak": alg / (us * 1e-6) / 1e9 / PEAK_HBM_GBS, "passes": n}
+        log(f"sparsify {name}: {us:.1f} us per pass at L={L}, M={M}: {alg / (us * 1e-6) / 1e9:.0f} GB/s algorithmic")
+    return {"kernel": "sparsify_residual", "L": L, "M": M, **out}
+
+
 STENCILS = [  # (name, theta_interp, s, fh_d, log_r)
     ("index-lagrange s=10 (default)", 0, 10, 0, False),
     ("theta-lagrange s=10", 1, 10, 0, False),
@@ -498,6 +536,8 @@ def main() -> int:
                     help="only the large-grid configuration: 16 solves at L=8192 in one pool")
     ap.add_argument("--stencils", action="store_true",
                     help="only the cost and accuracy of the theta-stencil schemes and the log-R option")
+    ap.add_argument("--sparsify", action="store_true",
+                    help="only the sparsification residual kernel at L=4096, M=4096 (one pass, nothing removed)")
     ap.add_argument("--kernel-slices", type=int, default=2500,
                     help="history slices of --kernel (the solver's steady state holds about 2500)")
     args = ap.parse_args()
@@ -520,6 +560,9 @@ def main() -> int:
         return 0
     if args.c5:
         print(json.dumps(large_grid_c5(pk, torch)), flush=True)
+        return 0
+    if args.sparsify:
+        print(json.dumps(sparsify_bench(pk, torch)), flush=True)
         return 0
     prec_name = args.precision
     other = "fp32c" if prec_name == "fp64" else "fp64"

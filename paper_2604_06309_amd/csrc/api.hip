@@ -145,6 +145,7 @@ Layout make_layout(const dmfe_params& p) {
         lo.eps = take(sizeof(double));
         lo.diag = take(2 * sizeof(double));
         lo.eps_n = take(Mc * sizeof(double));
+        lo.eps_part = take(2 * size_t(sparsify_chunks(int(L))) * Mc * sizeof(double));
         lo.obs = take(2 * Mc * sizeof(double));
         lo.rhs_y = take(L * sizeof(YPoint));
         lo.rhs_k = take(L * sizeof(YPoint));
@@ -344,7 +345,8 @@ dmfe_status sparsify_pass(dmfe_handle* h, int64_t* removed_out) {
     double* eps_n = h->at<double>(h->lo.eps_n);
     auto* ev = timing_begin(h, DMFE_K_SPARSIFY, 0);
     HCHK(launch_sparsify_residual(h->L, 1, count, h->at<double>(h->lo.thist), h->at<int>(h->lo.slot),
-                                  h->at<void>(h->lo.hist), h->fp32, eps_n, h->stream));
+                                  h->at<void>(h->lo.hist), h->fp32, eps_n, h->at<double>(h->lo.eps_part), h->Mc,
+                                  h->stream));
     timing_end(h, ev);
     std::vector<double> e(M, -1.0);
     HCHK(hipMemcpyAsync(e.data() + 1, eps_n + 1, sizeof(double) * count, hipMemcpyDeviceToHost, h->stream));

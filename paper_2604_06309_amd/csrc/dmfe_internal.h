@@ -106,8 +106,11 @@ hipError_t launch_append(int L, const YPoint* y, void* slot_dst, int fp32, LogPo
 hipError_t launch_log_mirror(int L, int count, const int* slot, const void* hist, int fp32, LogPoint* lhist,
                              hipStream_t st);
 hipError_t launch_load_state(int L, const void* slot_src, int fp32, YPoint* y, hipStream_t st);
+// part: scratch of 2 * sparsify_chunks(L) * stride doubles (stride >= first + count + 1)
+int sparsify_chunks(int L);
 hipError_t launch_sparsify_residual(int L, int first, int count, const double* thist, const int* slot,
-                                    const void* hist, int fp32, double* eps_n, hipStream_t st);
+                                    const void* hist, int fp32, double* eps_n, double* part, int stride,
+                                    hipStream_t st);
 hipError_t launch_slice_observables(const Model& m, int L, const double* nu, int count, const double* thist,
                                     const int* slot, const void* hist, int fp32, double* E, double* mu,
                                     hipStream_t st);

@@ -21,7 +21,8 @@ struct Tableau {
 };
 
 struct Layout {
-    size_t hist, lhist, thist, slot, th, thc, nu, bw, X, Xd, y, ys, ynew, k, mue, eps, diag, eps_n, obs, rhs_y, rhs_k, io, total;
+    size_t hist, lhist, thist, slot, th, thc, nu, bw, X, Xd, y, ys, ynew, k, mue, eps, diag, eps_n, eps_part, obs, rhs_y,
+        rhs_k, io, total;
     // uniform
     size_t uC, uR, uE, uy0, uy1, uys, uk;
 };

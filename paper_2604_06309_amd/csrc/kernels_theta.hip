@@ -855,38 +855,117 @@ constexpr double kUnitRoundoff32 = 5.9604644775390625e-8;  // 2^-24
 // Delta = H[n-1,n] + H[n,n+1] - H[n-1,n+1].  For an FP32 history the rounding
 // allowance is subtracted (never below zero), so a slice is kept only if its
 // residual exceeds what the storage precision can resolve by eps/10.
+//
+// A block owns a run of kSpK consecutive candidates and a chunk of kSpChunk
+// nodes: each thread slides a three-slice window along the run at its nodes,
+// so every slice of the run is read once (plus the two slices around it)
+// instead of once per candidate that touches it.  The partial sums of the
+// chunks go to part[chunk][n] (and the rounding allowance to bnd[chunk][n]);
+// k_sparsify_final adds the chunks in a fixed order.
+constexpr int kSpK = 16;        // candidates per block
+constexpr int kSpNpt = 4;       // nodes per thread
+constexpr int kSpThreads = 256;
+constexpr int kSpChunk = kSpThreads * kSpNpt;
+
 template <class HP>
-__global__ __launch_bounds__(256) void k_sparsify_residual(int L, int first, const double* __restrict__ thist,
-                                                           const int* __restrict__ slot, const HP* __restrict__ hist,
-                                                           double* __restrict__ eps_n) {
-    __shared__ double sh[16];
-    const int n = first + blockIdx.x;
-    const HP* pa = hist + size_t(slot[n - 1]) * L;
-    const HP* pc = hist + size_t(slot[n]) * L;
-    const HP* pb = hist + size_t(slot[n + 1]) * L;
-    const double h1 = thist[n] - thist[n - 1], h2 = thist[n + 1] - thist[n], h3 = thist[n + 1] - thist[n - 1];
-    const double ka = 0.5 * h2, kc = 0.5 * h3, kb = 0.5 * h1;
-    const double qa = fabs(h1 * h1 - h3 * h3) * (1.0 / 12.0), qc = fabs(h2 * h2 - h1 * h1) * (1.0 / 12.0),
-                 qb = fabs(h3 * h3 - h2 * h2) * (1.0 / 12.0);
-    double e = 0.0, bound = 0.0;
-    for (int i = threadIdx.x; i < L; i += blockDim.x) {
-        const HPoint va = up(pa[i]), vc = up(pc[i]), vb = up(pb[i]);
-        const double dc = herm_int(h1, va.c, va.dc, vc.c, vc.dc) + herm_int(h2, vc.c, vc.dc, vb.c, vb.dc) -
-                          herm_int(h3, va.c, va.dc, vb.c, vb.dc);
-        const double dr = herm_int(h1, va.r, va.dr, vc.r, vc.dr) + herm_int(h2, vc.r, vc.dr, vb.r, vb.dr) -
-                          herm_int(h3, va.r, va.dr, vb.r, vb.dr);
-        e += fabs(dc) + fabs(dr);
-        if (RoundingAllowance<HP>::on)
-            bound += ka * (fabs(va.c) + fabs(va.r)) + kc * (fabs(vc.c) + fabs(vc.r)) + kb * (fabs(vb.c) + fabs(vb.r)) +
-                     qa * (fabs(va.dc) + fabs(va.dr)) + qc * (fabs(vc.dc) + fabs(vc.dr)) +
-                     qb * (fabs(vb.dc) + fabs(vb.dr));
+__global__ __launch_bounds__(kSpThreads) void k_sparsify_part(int L, int first, int count, int stride,
+                                                              const double* __restrict__ thist,
+                                                              const int* __restrict__ slot,
+                                                              const HP* __restrict__ hist, double* __restrict__ part,
+                                                              double* __restrict__ bnd) {
+    __shared__ double red[kSpThreads / kWave][kSpK][2];
+    constexpr bool fp32 = RoundingAllowance<HP>::on;
+    const int n0 = first + int(blockIdx.x) * kSpK;       // first candidate of the run
+    const int kc = min(kSpK, first + count - n0);        // candidates in this run
+    const int i0 = int(blockIdx.y) * kSpChunk + int(threadIdx.x);
+    double e[kSpK], b[kSpK];
+#pragma unroll
+    for (int c = 0; c < kSpK; ++c) e[c] = b[c] = 0.0;
+    // the run's slices n0-1 .. n0+kc (uniform per block)
+    HPoint va[kSpNpt], vc[kSpNpt];
+    const HP* s0 = hist + size_t(slot[n0 - 1]) * L;
+    const HP* s1 = hist + size_t(slot[n0]) * L;
+#pragma unroll
+    for (int q = 0; q < kSpNpt; ++q) {
+        const int i = i0 + q * kSpThreads;
+        va[q] = vc[q] = HPoint{0.0, 0.0, 0.0, 0.0};
+        if (i < L) {
+            va[q] = up(s0[i]);
+            vc[q] = up(s1[i]);
+        }
     }
-    e = block_sum(e, sh);
-    if (RoundingAllowance<HP>::on) {
-        bound = block_sum(bound, sh) * kUnitRoundoff32;
-        e = e > bound ? e - bound : 0.0;
+#pragma unroll
+    for (int c = 0; c < kSpK; ++c) {
+        if (c < kc) {
+            const int n = n0 + c;
+            const double tm = thist[n - 1], tn = thist[n], tp = thist[n + 1];
+            const double h1 = tn - tm, h2 = tp - tn, h3 = tp - tm;
+            const HP* sb = hist + size_t(slot[n + 1]) * L;
+            const double ka = 0.5 * h2, kcn = 0.5 * h3, kb = 0.5 * h1;
+            const double qa = fabs(h1 * h1 - h3 * h3) * (1.0 / 12.0), qc = fabs(h2 * h2 - h1 * h1) * (1.0 / 12.0),
+                         qb = fabs(h3 * h3 - h2 * h2) * (1.0 / 12.0);
+#pragma unroll
+            for (int q = 0; q < kSpNpt; ++q) {
+                const int i = i0 + q * kSpThreads;
+                HPoint vb = HPoint{0.0, 0.0, 0.0, 0.0};
+                if (i < L) vb = up(sb[i]);
+                const HPoint& A = va[q];
+                const HPoint& Cc = vc[q];
+                const double dc = herm_int(h1, A.c, A.dc, Cc.c, Cc.dc) + herm_int(h2, Cc.c, Cc.dc, vb.c, vb.dc) -
+                                  herm_int(h3, A.c, A.dc, vb.c, vb.dc);
+                const double dr = herm_int(h1, A.r, A.dr, Cc.r, Cc.dr) + herm_int(h2, Cc.r, Cc.dr, vb.r, vb.dr) -
+                                  herm_int(h3, A.r, A.dr, vb.r, vb.dr);
+                e[c] += fabs(dc) + fabs(dr);
+                if (fp32)
+                    b[c] += ka * (fabs(A.c) + fabs(A.r)) + kcn * (fabs(Cc.c) + fabs(Cc.r)) +
+                            kb * (fabs(vb.c) + fabs(vb.r)) + qa * (fabs(A.dc) + fabs(A.dr)) +
+                            qc * (fabs(Cc.dc) + fabs(Cc.dr)) + qb * (fabs(vb.dc) + fabs(vb.dr));
+                va[q] = vc[q];
+                vc[q] = vb;
+            }
+        }
     }
-    if (threadIdx.x == 0) eps_n[n] = e;
+    // block sums of the run's candidates, in a fixed order
+    const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int c = 0; c < kSpK; ++c) {
+        const double se = wave_sum(e[c]);
+        const double sb = fp32 ? wave_sum(b[c]) : 0.0;
+        if (lane == 0) {
+            red[w][c][0] = se;
+            red[w][c][1] = sb;
+        }
+    }
+    __syncthreads();
+    if (int(threadIdx.x) < kc) {
+        const int c = threadIdx.x;
+        double se = 0.0, sb = 0.0;
+        for (int q = 0; q < kSpThreads / kWave; ++q) {
+            se += red[q][c][0];
+            sb += red[q][c][1];
+        }
+        part[size_t(blockIdx.y) * stride + n0 + c] = se;
+        if (fp32) bnd[size_t(blockIdx.y) * stride + n0 + c] = sb;
+    }
+}
+
+// eps_n from the chunks' partial sums, in chunk order.
+__global__ void k_sparsify_final(int first, int count, int chunks, int stride, int fp32,
+                                 const double* __restrict__ part, const double* __restrict__ bnd,
+                                 double* __restrict__ eps_n) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= count) return;
+    const int n = first + k;
+    double e = 0.0, bd = 0.0;
+    for (int q = 0; q < chunks; ++q) {
+        e += part[size_t(q) * stride + n];
+        if (fp32) bd += bnd[size_t(q) * stride + n];
+    }
+    if (fp32) {
+        bd *= kUnitRoundoff32;
+        e = e > bd ? e - bd : 0.0;
+    }
+    eps_n[n] = e;
 }
 
 // ---------------------------------------------------------------- observables and copies
@@ -1121,15 +1200,24 @@ hipError_t launch_load_state(int L, const void* slot_src, int fp32, YPoint* y, h
     return hipGetLastError();
 }
 
+int sparsify_chunks(int L) { return (L + kSpChunk - 1) / kSpChunk; }
+
 hipError_t launch_sparsify_residual(int L, int first, int count, const double* thist, const int* slot,
-                                    const void* hist, int fp32, double* eps_n, hipStream_t st) {
+                                    const void* hist, int fp32, double* eps_n, double* part, int stride,
+                                    hipStream_t st) {
     if (count <= 0) return hipSuccess;
+    if (first < 1 || first + count + 1 > stride) return hipErrorInvalidValue;  // slices first-1 .. first+count
+    const int chunks = sparsify_chunks(L);
+    const dim3 grid(unsigned((count + kSpK - 1) / kSpK), unsigned(chunks));
+    double* bnd = part + size_t(chunks) * stride;
     if (fp32)
-        hipLaunchKernelGGL(k_sparsify_residual<HPoint32>, dim3(count), dim3(256), 0, st, L, first, thist, slot,
-                           static_cast<const HPoint32*>(hist), eps_n);
+        hipLaunchKernelGGL(k_sparsify_part<HPoint32>, grid, dim3(kSpThreads), 0, st, L, first, count, stride, thist,
+                           slot, static_cast<const HPoint32*>(hist), part, bnd);
     else
-        hipLaunchKernelGGL(k_sparsify_residual<HPoint>, dim3(count), dim3(256), 0, st, L, first, thist, slot,
-                           static_cast<const HPoint*>(hist), eps_n);
+        hipLaunchKernelGGL(k_sparsify_part<HPoint>, grid, dim3(kSpThreads), 0, st, L, first, count, stride, thist,
+                           slot, static_cast<const HPoint*>(hist), part, bnd);
+    hipLaunchKernelGGL(k_sparsify_final, dim3(nblk(count, 256)), dim3(256), 0, st, first, count, chunks, stride, fp32,
+                       part, bnd, eps_n);
     return hipGetLastError();
 }
 

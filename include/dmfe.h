@@ -266,6 +266,7 @@ dmfe_status dmfe_set_history(dmfe_handle *h, int64_t M, int64_t nb, const double
 dmfe_status dmfe_rhs(dmfe_handle *h, double t, const double *yC, const double *yR, int64_t nb, double *outC,
                      double *outR, double *mu, double *diag);
 
+
 void dmfe_destroy(dmfe_handle *h);
 
 /*
@@ -395,6 +396,13 @@ dmfe_status dmfe_pool_result(dmfe_pool *pool, uint64_t request_id, dmfe_step_inf
 /* dmfe_read on an admitted or finished solve. */
 dmfe_status dmfe_pool_read(dmfe_pool *pool, uint64_t request_id, int32_t field, int64_t first, int64_t count, void *dst,
                            size_t dst_bytes, int32_t dst_on_device, size_t *needed_bytes);
+/* dmfe_set_history on an admitted, running solve that is between two steps (a
+ * solve is admitted by dmfe_pool_run, also with max_ticks = 0): resumes a solve
+ * from a stored history inside the pool.  DMFE_ERR_INVALID for an unknown,
+ * queued or finished solve, or one whose step is in flight. */
+dmfe_status dmfe_pool_set_history(dmfe_pool *pool, uint64_t request_id, int64_t M, int64_t nb, const double *t_hist,
+                                  const double *C, const double *R, const double *dC, const double *dR,
+                                  int32_t src_on_device, double dt, int32_t scheme);
 /* Free a finished solve's memory. */
 dmfe_status dmfe_pool_release(dmfe_pool *pool, uint64_t request_id);
 void dmfe_pool_destroy(dmfe_pool *pool);

@@ -116,6 +116,7 @@ SIGNATURES = {
                                 ctypes.POINTER(dmfe_pool_times)]),
     "dmfe_pool_read": (_i32, [_vp, ctypes.c_uint64, _i32, _i64, _i64, _vp, _sz, _i32, ctypes.POINTER(_sz)]),
     "dmfe_pool_release": (_i32, [_vp, ctypes.c_uint64]),
+    "dmfe_pool_set_history": (_i32, [_vp, ctypes.c_uint64, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _i32, _d, _i32]),
     "dmfe_pool_destroy": (None, [_vp]),
     "dmfe_timing_read": (_i32, [_vp, _i32, ctypes.POINTER(_i64), ctypes.POINTER(_d), ctypes.POINTER(_i64)]),
 }
@@ -224,9 +225,7 @@ def dmfe_get_info(h: int) -> dmfe_step_info:
     return info
 
 
-def dmfe_set_history(h: int, t_hist, C, R, dC, dR, nb: Optional[int] = None, dt: float = 0.0,
-                     scheme: int = -1) -> None:
-    """Host numpy arrays ([M], [M, L] x4) or CUDA tensors of the same shapes."""
+def _history_args(t_hist, C, R, dC, dR, nb):
     M = int(len(t_hist))
     nb = M if nb is None else int(nb)
     if isinstance(C, np.ndarray):
@@ -235,7 +234,21 @@ def dmfe_set_history(h: int, t_hist, C, R, dC, dR, nb: Optional[int] = None, dt:
     else:
         arrs = [a.contiguous().double() for a in (t_hist, C, R, dC, dR)]
         ptrs, on_dev = [a.data_ptr() for a in arrs], 1
+    return M, nb, arrs, ptrs, on_dev
+
+
+def dmfe_set_history(h: int, t_hist, C, R, dC, dR, nb: Optional[int] = None, dt: float = 0.0,
+                     scheme: int = -1) -> None:
+    """Host numpy arrays ([M], [M, L] x4) or CUDA tensors of the same shapes."""
+    M, nb, arrs, ptrs, on_dev = _history_args(t_hist, C, R, dC, dR, nb)
     _check(lib().dmfe_set_history(h, M, nb, *ptrs, on_dev, dt, scheme), "dmfe_set_history")
+
+
+def dmfe_pool_set_history(pool: int, rid: int, t_hist, C, R, dC, dR, nb: Optional[int] = None, dt: float = 0.0,
+                          scheme: int = -1) -> None:
+    """dmfe_set_history on an admitted pooled solve between two steps."""
+    M, nb, arrs, ptrs, on_dev = _history_args(t_hist, C, R, dC, dR, nb)
+    _check(lib().dmfe_pool_set_history(pool, rid, M, nb, *ptrs, on_dev, dt, scheme), "dmfe_pool_set_history")
 
 
 def dmfe_rhs(h: int, t: float, yC, yR, nb: int):
@@ -443,6 +456,9 @@ class Pool:
 
     def release(self, rid: int) -> None:
         dmfe_pool_release(self.p, rid)
+
+    def set_history(self, rid: int, t_hist, C, R, dC, dR, nb=None, dt: float = 0.0, scheme: int = -1) -> None:
+        dmfe_pool_set_history(self.p, rid, t_hist, C, R, dC, dR, nb, dt, scheme)
 
     def close(self):
         if getattr(self, "p", None):

@@ -266,7 +266,22 @@ void timing_drain(dmfe_handle* h) {
     h->ev_pending.clear();
 }
 
+StageBufs handle_bufs(const dmfe_handle* h) {
+    StageBufs b{};
+    b.stage = stage_slot(h);
+    LogPoint* lm = log_mirror(h);
+    b.lstage = lm ? lm + size_t(h->Mc) * h->L : nullptr;
+    b.mue = h->at<double>(h->lo.mue);
+    b.diag = h->at<double>(h->lo.diag);
+    return b;
+}
+
 StageArgs stage_args(const dmfe_handle* h, double t, int nb, const YPoint* y, YPoint* kout, void* store) {
+    return stage_args(h, t, nb, y, kout, store, handle_bufs(h));
+}
+
+StageArgs stage_args(const dmfe_handle* h, double t, int nb, const YPoint* y, YPoint* kout, void* store,
+                     const StageBufs& b) {
     StageArgs a{};
     a.L = h->L;
     a.nb = nb;
@@ -280,18 +295,19 @@ StageArgs stage_args(const dmfe_handle* h, double t, int nb, const YPoint* y, YP
     a.thist = h->at<double>(h->lo.thist);
     a.slot = h->at<int>(h->lo.slot);
     a.hist = h->at<void>(h->lo.hist);
-    a.stage = stage_slot(h);
+    a.stage = b.stage;
     a.fp32 = h->fp32;
     a.y = y;
-    a.mue = h->at<double>(h->lo.mue);
+    a.mue = b.mue;
     a.kout = kout;
     a.store = store;
-    a.diag = h->at<double>(h->lo.diag);
+    a.diag = b.diag;
     a.interp = h->p.theta_interp;
     a.log_r = h->p.log_r;
     a.bw = h->at<double>(h->lo.bw);
     for (int k = 0; k < 16; ++k) a.fh_c[k] = h->fh_c[k];
     a.lhist = log_mirror(h);
+    a.lstage = b.lstage;
     a.m = h->m;
     return a;
 }
@@ -306,17 +322,21 @@ dmfe_status rebuild_log_mirror(dmfe_handle* h) {
 }
 
 // one right-hand-side evaluation: mu(t) then the history integrals
-dmfe_status eval_rhs(dmfe_handle* h, double t, int nb, const YPoint* y, YPoint* kout, void* store) {
-    auto* e1 = timing_begin(h, DMFE_K_STAGE_PREP, 0);
-    LogPoint* lm = log_mirror(h);
-    HCHK(launch_stage_prep(h->m, h->L, t, h->at<double>(h->lo.nu), y, h->at<double>(h->lo.mue), stage_slot(h),
-                           h->fp32, lm ? lm + size_t(h->Mc) * h->L : nullptr, h->stream));
+dmfe_status eval_rhs(dmfe_handle* h, double t, int nb, const YPoint* y, YPoint* kout, void* store,
+                     const StageBufs& b, bool timed) {
+    auto* e1 = timed ? timing_begin(h, DMFE_K_STAGE_PREP, 0) : nullptr;
+    HCHK(launch_stage_prep(h->m, h->L, t, h->at<double>(h->lo.nu), y, b.mue, b.stage, h->fp32, b.lstage,
+                           h->stream));
     timing_end(h, e1);
-    auto* e2 = timing_begin(h, DMFE_K_HIST_INTEGRAL, nb);
-    HCHK(launch_hist_integral(stage_args(h, t, nb, y, kout, store), h->s, h->stream));
+    auto* e2 = timed ? timing_begin(h, DMFE_K_HIST_INTEGRAL, nb) : nullptr;
+    HCHK(launch_hist_integral(stage_args(h, t, nb, y, kout, store, b), h->s, h->stream));
     timing_end(h, e2);
     h->rhs_evals += 1;
     return DMFE_OK;
+}
+
+dmfe_status eval_rhs(dmfe_handle* h, double t, int nb, const YPoint* y, YPoint* kout, void* store) {
+    return eval_rhs(h, t, nb, y, kout, store, handle_bufs(h), true);
 }
 
 size_t point_bytes(const dmfe_handle* h) { return h->fp32 ? sizeof(HPoint32) : sizeof(HPoint); }

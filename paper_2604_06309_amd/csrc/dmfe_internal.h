@@ -76,7 +76,8 @@ struct StageArgs {
     int log_r;           // interpolate log R (falls back to R on non-positive stencils)
     const double* bw;    // barycentric stencil coefficients [L-s+1][s+1] (schemes other than index Lagrange)
     double fh_c[16];     // index Floater-Hormann: the coefficients, the same for every stencil base
-    LogPoint* lhist;     // log-R option: log mirror of the history slots and the stage slot [M_cap+1][L], else null
+    LogPoint* lhist;     // log-R option: log mirror of the history slots [M_cap][L], else null
+    const LogPoint* lstage;  // log-R option: log mirror of the stage slot [L], else null
 };
 
 // Run-constant data of the theta grid used by the coordinate precompute.

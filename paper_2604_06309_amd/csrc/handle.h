@@ -119,10 +119,24 @@ dmfe_handle::EvPair* timing_begin(dmfe_handle* h, int kernel, int64_t slices);
 void timing_end(dmfe_handle* h, dmfe_handle::EvPair* p);
 void timing_drain(dmfe_handle* h);
 
+// Per-evaluation buffers of one right-hand side: the stage slice in history format
+// and its log mirror (log-R option), mu(t) and E(t), the computed diagonal values.
+struct StageBufs {
+    void* stage;
+    LogPoint* lstage;
+    double* mue;
+    double* diag;
+};
+StageBufs handle_bufs(const dmfe_handle* h);  // the handle's own, in its workspace
+StageArgs stage_args(const dmfe_handle* h, double t, int nb, const YPoint* y, YPoint* kout, void* store,
+                     const StageBufs& b);
 StageArgs stage_args(const dmfe_handle* h, double t, int nb, const YPoint* y, YPoint* kout, void* store);
 void* stage_slot(const dmfe_handle* h);  // the stage slice in history format, after the Mc slots
 LogPoint* log_mirror(const dmfe_handle* h);  // log-R option: mirror of the Mc slots and the stage slot, else null
 dmfe_status rebuild_log_mirror(dmfe_handle* h);  // mirror of the M stored slices from their stored values
+// one right-hand side into b's buffers; `timed` records the launches for dmfe_timing
+dmfe_status eval_rhs(dmfe_handle* h, double t, int nb, const YPoint* y, YPoint* kout, void* store,
+                     const StageBufs& b, bool timed);
 dmfe_status eval_rhs(dmfe_handle* h, double t, int nb, const YPoint* y, YPoint* kout, void* store);
 size_t point_bytes(const dmfe_handle* h);
 void* slot_ptr(dmfe_handle* h, int slot);

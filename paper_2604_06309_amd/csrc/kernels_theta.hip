@@ -10,6 +10,9 @@
 //   t_n, slot of slice n       logical order (slot indirection: sparsify and
 //                              revert never move slice data)
 #include <cmath>
+#include <map>
+#include <mutex>
+#include <utility>
 
 #include "dmfe_internal.h"
 
@@ -497,9 +500,13 @@ __device__ __forceinline__ void hist_integral_block(const StageArgs& a, int row_
     }
     constexpr bool use_log = var_log(VAR);
     // log mirror rows of the stage slot and of the row's two slots (same offsets as the history)
-    const LogPoint* lstage = use_log ? a.lhist + (stage - hist) : nullptr;
-    const LogPoint* lc0 = use_log ? a.lhist + (c0p - hist) : nullptr;
-    const LogPoint* lc1 = use_log ? a.lhist + (c1p - hist) : nullptr;
+    // the stage slot may live outside the history (its mirror is a.lstage)
+    auto mirror = [&](const HP* slotp) -> const LogPoint* {
+        return slotp == stage ? a.lstage : a.lhist + (slotp - hist);
+    };
+    const LogPoint* lstage = use_log ? a.lstage : nullptr;
+    const LogPoint* lc0 = use_log ? mirror(c0p) : nullptr;
+    const LogPoint* lc1 = use_log ? mirror(c1p) : nullptr;
     const double* Xa = a.X + size_t(j) * L;          // row j, read forwards
     const double* Xb = a.X + size_t(L - 1 - j) * L;  // row L-1-j, read backwards
     const double* Xdj = a.Xd + size_t(j) * L;
@@ -620,8 +627,8 @@ __device__ __forceinline__ void hist_integral_block(const StageArgs& a, int row_
                 dR = h00 * r0 + h10 * dr0 + h01 * r1 + h11 * dr1;
                 if constexpr (use_log) {
                     double lv0, ld0, lv1, ld1;
-                    log_interp_slot<S>(a.lhist + (p0 - hist), base, wd, lv0, ld0);
-                    log_interp_slot<S>(a.lhist + (p1 - hist), base, wd, lv1, ld1);
+                    log_interp_slot<S>(mirror(p0), base, wd, lv0, ld0);
+                    log_interp_slot<S>(mirror(p1), base, wd, lv1, ld1);
                     const double l = h00 * lv0 + h10 * ld0 + h01 * lv1 + h11 * ld1;
                     if (!__builtin_isnan(l)) dR = exp(l);
                 }
@@ -1062,10 +1069,22 @@ static size_t max_lds() {
     return v;
 }
 
+// Raise a kernel's dynamic-LDS limit when a launch needs more than the default
+// 64 KB.  The attribute is set once per (device, kernel) for the largest size
+// seen so far, not on every launch.
 template <class K>
 static void allow_lds(K kernel, size_t bytes) {
-    if (bytes > 65536) (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
+    if (bytes <= 65536) return;
+    static std::mutex mu;
+    static std::map<std::pair<int, const void*>, size_t> done;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    const auto key = std::make_pair(dev, reinterpret_cast<const void*>(kernel));
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = done.find(key);
+    if (it != done.end() && it->second >= bytes) return;
+    if (hipFuncSetAttribute(key.second, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes)) == hipSuccess)
+        done[key] = bytes;
 }
 
 template <int S, class HP, bool YL, int VAR, bool TG = false>

@@ -62,7 +62,8 @@ struct dmfe_pool {
     int64_t ticks = 0;
     // batch descriptors: device buffers and pinned host staging
     char* d_desc = nullptr;
-    char* h_desc = nullptr;
+    char* h_desc = nullptr;  // descriptors filled per tick, laid out for max_instances
+    char* h_pack = nullptr;  // the same, packed to the tick's counts for one short upload
     size_t desc_bytes = 0;
     double* d_eps = nullptr;
     double* h_eps = nullptr;
@@ -272,15 +273,38 @@ dmfe_status tick(dmfe_pool* P) {
     a_fbh[n_eval] = hist_blocks;
     a_fbc[n_comb] = comb_blocks;
     if (n_eval + n_comb + n_fin > 0) {
-        HCHK(hipMemcpyAsync(P->d_desc, P->h_desc, dl.total, hipMemcpyHostToDevice, P->stream));
+        // upload only this tick's entries: the sections packed to their counts
+        DescLayout pl{};
+        size_t o = 0;
+        pl.args = o;
+        o += up256(sizeof(StageArgs) * n_eval);
+        pl.fb_hist = o;
+        o += up256(sizeof(int) * (n_eval + 1));
+        pl.comb = o;
+        o += up256(sizeof(CombineDesc) * n_comb);
+        pl.fb_comb = o;
+        o += up256(sizeof(int) * (n_comb + 1));
+        pl.prep = o;
+        o += up256(sizeof(PrepDesc) * n_eval);
+        pl.fin = o;
+        o += up256(sizeof(FinishDesc) * n_fin);
+        pl.total = o;
+        std::memcpy(P->h_pack + pl.args, P->h_desc + dl.args, sizeof(StageArgs) * n_eval);
+        std::memcpy(P->h_pack + pl.fb_hist, P->h_desc + dl.fb_hist, sizeof(int) * (n_eval + 1));
+        std::memcpy(P->h_pack + pl.comb, P->h_desc + dl.comb, sizeof(CombineDesc) * n_comb);
+        std::memcpy(P->h_pack + pl.fb_comb, P->h_desc + dl.fb_comb, sizeof(int) * (n_comb + 1));
+        std::memcpy(P->h_pack + pl.prep, P->h_desc + dl.prep, sizeof(PrepDesc) * n_eval);
+        std::memcpy(P->h_pack + pl.fin, P->h_desc + dl.fin, sizeof(FinishDesc) * n_fin);
+        // the previous tick ended with a stream synchronisation, so h_pack is free to refill
+        HCHK(hipMemcpyAsync(P->d_desc, P->h_pack, pl.total, hipMemcpyHostToDevice, P->stream));
         const char* D = P->d_desc;
-        HCHK(launch_rk_combine_multi(reinterpret_cast<const CombineDesc*>(D + dl.comb),
-                                     reinterpret_cast<const int*>(D + dl.fb_comb), n_comb, comb_blocks, P->stream));
-        HCHK(launch_stage_prep_multi(reinterpret_cast<const PrepDesc*>(D + dl.prep), n_eval, pmax, P->stream));
-        HCHK(launch_hist_integral_multi(reinterpret_cast<const StageArgs*>(D + dl.args),
-                                        reinterpret_cast<const int*>(D + dl.fb_hist), n_eval, hist_blocks, 10, pmax,
+        HCHK(launch_rk_combine_multi(reinterpret_cast<const CombineDesc*>(D + pl.comb),
+                                     reinterpret_cast<const int*>(D + pl.fb_comb), n_comb, comb_blocks, P->stream));
+        HCHK(launch_stage_prep_multi(reinterpret_cast<const PrepDesc*>(D + pl.prep), n_eval, pmax, P->stream));
+        HCHK(launch_hist_integral_multi(reinterpret_cast<const StageArgs*>(D + pl.args),
+                                        reinterpret_cast<const int*>(D + pl.fb_hist), n_eval, hist_blocks, 10, pmax,
                                         fp32 < 0 ? 0 : fp32, nb_max, P->stream));
-        HCHK(launch_rk_finish_multi(reinterpret_cast<const FinishDesc*>(D + dl.fin), n_fin, P->stream));
+        HCHK(launch_rk_finish_multi(reinterpret_cast<const FinishDesc*>(D + pl.fin), n_fin, P->stream));
         if (n_fin > 0)
             HCHK(hipMemcpyAsync(P->h_eps, P->d_eps, sizeof(double) * n_fin, hipMemcpyDeviceToHost, P->stream));
         HCHK(hipStreamSynchronize(P->stream));
@@ -330,6 +354,7 @@ dmfe_status dmfe_pool_create(const dmfe_pool_params* pp, const dmfe_resources* r
     P->desc_bytes = dl.total;
     if (hipMalloc(reinterpret_cast<void**>(&P->d_desc), dl.total) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&P->h_desc), dl.total, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&P->h_pack), dl.total, hipHostMallocDefault) != hipSuccess ||
         hipMalloc(reinterpret_cast<void**>(&P->d_eps), sizeof(double) * pp->max_instances) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&P->h_eps), sizeof(double) * pp->max_instances,
                       hipHostMallocDefault) != hipSuccess) {
@@ -425,6 +450,16 @@ dmfe_status dmfe_pool_read(dmfe_pool* P, uint64_t id, int32_t field, int64_t fir
     return dmfe_read(q->h, field, first, count, dst, dst_bytes, dst_on_device, needed_bytes);
 }
 
+dmfe_status dmfe_pool_set_history(dmfe_pool* P, uint64_t id, int64_t M, int64_t nb, const double* t_hist,
+                                  const double* C, const double* R, const double* dC, const double* dR,
+                                  int32_t src_on_device, double dt, int32_t scheme) {
+    if (!P) return DMFE_ERR_INVALID;
+    Instance* q = find_live(P, id);
+    // admitted, still running, and between two steps (no stage of it in flight)
+    if (!q || !q->h || q->done || q->h->cur.active) return DMFE_ERR_INVALID;
+    return dmfe_set_history(q->h, M, nb, t_hist, C, R, dC, dR, src_on_device, dt, scheme);
+}
+
 dmfe_status dmfe_pool_release(dmfe_pool* P, uint64_t id) {
     if (!P) return DMFE_ERR_INVALID;
     for (size_t k = 0; k < P->live.size(); ++k) {
@@ -447,6 +482,7 @@ void dmfe_pool_destroy(dmfe_pool* P) {
         if (q.h) dmfe_destroy(q.h);
     if (P->d_desc) (void)hipFree(P->d_desc);
     if (P->h_desc) (void)hipHostFree(P->h_desc);
+    if (P->h_pack) (void)hipHostFree(P->h_pack);
     if (P->d_eps) (void)hipFree(P->d_eps);
     if (P->h_eps) (void)hipHostFree(P->h_eps);
     delete P;

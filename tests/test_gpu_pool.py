@@ -117,3 +117,47 @@ def test_sixteen_large_instances_stepped_together(precision):
     np.testing.assert_array_equal(s.read(pk.F_R), ref[2])
     s.close()
     say(f"  16 instances bitwise equal to each other and to the solo solve after {steps} steps, M={info.M}")
+
+
+@pytest.mark.parametrize("precision", [pk.FP64, pk.FP32_COMP])
+def test_sixteen_large_instances_with_a_long_history(precision):
+    """The large-grid stress case with a history of 400 stored slices: the solve is
+    first run alone for 400 steps; its stored history then resumes the 16 pooled
+    solves (dmfe_pool_set_history) and, once more, the solve alone
+    (dmfe_set_history); all are stepped for 60 ticks' worth of stages.  Every
+    pooled instance stays bitwise equal to the others and to the solo solve after
+    the same number of steps."""
+    say(f"16 instances at L=8192 with 400 stored slices, precision={precision}")
+    L, M = 8192, 401
+    p = pk.make_params({2: 0.3, 4: 0.7}, 0.45, t_max=1e7, L=L, M_cap=512, eps=1e-8, dt0=1e-3, dt_min=1e-12,
+                       precision=precision)
+    s = pk.Solver(p)
+    _, info0 = s.step(float("inf"), M - 1)
+    assert info0.M == M and info0.nb_valid == M
+    times, C, R, dC, dR = (s.read(f) for f in (pk.F_T_GRID, pk.F_C, pk.F_R, pk.F_DC, pk.F_DR))
+    dt0 = info0.dt
+    pool = pk.Pool(16 * pk.dmfe_footprint(p) + 4096, max_instances=16)
+    ids = [pool.submit(p) for _ in range(16)]
+    st = pool.run(0)  # admission only
+    assert st.running == 16
+    for rid in ids:
+        pool.set_history(rid, times, C, R, dC, dR, dt=dt0, scheme=pk.SCHEME_DP5)
+    st = pool.run(60)
+    assert st.running == 16
+    infos = [pool.result(rid)[0] for rid in ids]
+    steps = infos[0].accepted + infos[0].rejected
+    assert steps >= 5 and infos[0].M >= M
+    ref = [pool.read(ids[0], f, L=L) for f in (pk.F_T_GRID, pk.F_C, pk.F_R, pk.F_DC)]
+    for rid in ids[1:]:
+        for f, r in zip((pk.F_T_GRID, pk.F_C, pk.F_R, pk.F_DC), ref):
+            np.testing.assert_array_equal(pool.read(rid, f, L=L), r)
+    pool.close()
+    s.set_history(times, C, R, dC, dR, dt=dt0, scheme=pk.SCHEME_DP5)
+    a0 = s.info()
+    _, info = s.step(float("inf"), steps)
+    assert (info.accepted - a0.accepted, info.rejected - a0.rejected, info.M) == (infos[0].accepted,
+                                                                                  infos[0].rejected, infos[0].M)
+    for f, r in zip((pk.F_T_GRID, pk.F_C, pk.F_R, pk.F_DC), ref):
+        np.testing.assert_array_equal(s.read(f), r)
+    s.close()
+    say(f"  16 instances bitwise equal to each other and to the solo solve after {steps} steps, M={info.M}")

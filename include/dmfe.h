@@ -266,6 +266,22 @@ dmfe_status dmfe_set_history(dmfe_handle *h, int64_t M, int64_t nb, const double
 dmfe_status dmfe_rhs(dmfe_handle *h, double t, const double *yC, const double *yR, int64_t nb, double *outC,
                      double *outR, double *mu, double *diag);
 
+/*
+ * For callers that cannot allocate memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): dmfe_rhs with the same
+ * arguments, results and errors, but every transient buffer of the evaluation
+ * (the interleaved stage slice, its history-format copy and log mirror, the
+ * right-hand side before it is split into outC/outR, mu, E and the diagonal
+ * values) is taken from one static device array of the library instead of the
+ * handle's workspace.  No device or host memory is allocated and no timing
+ * events are recorded.  The array holds a grid of at most 16384 points (about
+ * 1.3 MB per device, kept until the process ends): DMFE_ERR_INVALID for a
+ * larger L.  All calls on one device share its array and leave their contents
+ * in it: calls that overlap in time on one device (two streams or two host
+ * threads) race and must be serialised by the caller.
+ */
+dmfe_status dmfe_rhs_noalloc(dmfe_handle *h, double t, const double *yC, const double *yR, int64_t nb,
+                             double *outC, double *outR, double *mu, double *diag);
 
 void dmfe_destroy(dmfe_handle *h);
 

@@ -95,6 +95,7 @@ SIGNATURES = {
     "dmfe_get_info": (_i32, [_vp, ctypes.POINTER(dmfe_step_info)]),
     "dmfe_set_history": (_i32, [_vp, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _i32, _d, _i32]),
     "dmfe_rhs": (_i32, [_vp, _d, _vp, _vp, _i64, _vp, _vp, _vp, _vp]),
+    "dmfe_rhs_noalloc": (_i32, [_vp, _d, _vp, _vp, _i64, _vp, _vp, _vp, _vp]),
     "dmfe_destroy": (None, [_vp]),
     "dmfe_status_string": (ctypes.c_char_p, [_i32]),
     "dmfe_last_error": (ctypes.c_char_p, []),
@@ -261,6 +262,17 @@ def dmfe_rhs(h: int, t: float, yC, yR, nb: int):
     _check(lib().dmfe_rhs(h, t, yC.data_ptr(), yR.data_ptr(), nb, outC.data_ptr(), outR.data_ptr(),
                           ctypes.byref(mu), _ptr(diag)), "dmfe_rhs")
     return outC, outR, mu.value, diag
+
+
+def dmfe_rhs_noalloc(h: int, t: float, yC, yR, nb: int, outC, outR):
+    """As dmfe_rhs, writing into the caller's CUDA float64 tensors outC, outR [L];
+    the library allocates nothing (its transient buffers are a static device array).
+    Returns mu, diag[2]."""
+    mu = ctypes.c_double()
+    diag = np.zeros(2)
+    _check(lib().dmfe_rhs_noalloc(h, t, yC.data_ptr(), yR.data_ptr(), nb, outC.data_ptr(), outR.data_ptr(),
+                                  ctypes.byref(mu), _ptr(diag)), "dmfe_rhs_noalloc")
+    return mu.value, diag
 
 
 def dmfe_timing(h: int, enable: bool) -> None:

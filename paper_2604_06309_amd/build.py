@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libdmfe.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["api.hip", "checkpoint.hip", "grid.cpp", "kernels_theta.hip", "kernels_uniform.hip", "pool.hip"]
+SOURCES = ["api.hip", "checkpoint.hip", "grid.cpp", "kernels_theta.hip", "kernels_uniform.hip", "noalloc.hip", "pool.hip"]
 ARCH = "gfx950"
 
 # Packed FP32 instructions are switched off for all device code.

@@ -230,8 +230,12 @@ def serving_sweep(pk, n: int = 24, seed: int = 20260406):
     pool = pk.Pool(arena, max_instances=256)
     t0 = time.perf_counter()
     nxt, tts, status = 0, [], []
+    t_log = t0
     while len(tts) < n:
         now = time.perf_counter() - t0
+        if time.perf_counter() - t_log > 20.0:
+            t_log = time.perf_counter()
+            log(f"c4 poisson: {len(tts)} of {n} done, {nxt} arrived after {now:.0f} s")
         while nxt < n and arrivals[nxt] <= now:
             pool.submit(reqs[nxt])
             nxt += 1
@@ -258,6 +262,124 @@ def serving_sweep(pk, n: int = 24, seed: int = 20260406):
     })
     log(f"serving: Poisson run {t_open:.1f} s, p50 {out['p50_time_to_solution_s']:.2f} s, "
         f"p99 {out['p99_time_to_solution_s']:.2f} s")
+    return out
+
+
+def c4_sweep(pk, torch, n: int = 128, tmax_range=(1e2, 1e3), seed: int = 20260406, part: str = "all") -> dict:
+    """The serving sweep (C4 shape, scaled in t_max): n requests with T ~ U[0.4, 1.2],
+    (a2^2, a3^2, a4^2) ~ Dirichlet(1,1,1), L uniform on {512, 1024, 2048, 4096}, history
+    cap L, eps = 1e-6, t_max log-uniform on tmax_range (the stated C4 range [1e2, 1e6]
+    is GPU-hours).  (a) FP32-comp: closed batch (all n submitted at once) -> capacity in
+    solves/s; then Poisson arrivals at 0.8 x capacity -> p50/p99 time to solution over
+    all n.  (b) FP64: closed batch.  (c) The batching gain on the small half
+    (L in {512, 1024}): the same requests pooled (closed batch) and one after another
+    (one solver each), in FP64 and in FP32-comp."""
+    import numpy as np
+    out = {"sweep": f"{n} requests: T~U[0.4,1.2], (a2^2,a3^2,a4^2)~Dirichlet(1,1,1), t_max~logU"
+                    f"[{tmax_range[0]:g},{tmax_range[1]:g}], L~U{{512,1024,2048,4096}}, history cap L, eps=1e-6, "
+                    f"seed {seed}"}
+    arena = int(0.6 * torch.cuda.mem_get_info()[0])
+
+    def closed(reqs, label):
+        pool = pk.Pool(arena, max_instances=256)
+        t0 = time.perf_counter()
+        ids = [pool.submit(p) for p in reqs]
+        done, status, svc, tts = 0, [], [], []
+        t_log = t0
+        while done < len(reqs):
+            pool.run(50)
+            if time.perf_counter() - t_log > 20.0:
+                t_log = time.perf_counter()
+                log(f"c4 {label}: {done} of {len(reqs)} done after {t_log - t0:.0f} s")
+            for rid in pool.poll():
+                _, tm = pool.result(rid)
+                status.append(tm.status)
+                svc.append(tm.service_s)
+                tts.append(tm.total_s)
+                pool.release(rid)
+                done += 1
+        wall = time.perf_counter() - t0
+        ticks = pool.run(0).ticks
+        pool.close()
+        log(f"c4 {label}: closed batch of {len(reqs)} in {wall:.1f} s ({len(reqs) / wall:.2f} solves/s, {ticks} ticks)")
+        return {"solves": len(reqs), "wall_s": wall, "solves_per_s": len(reqs) / wall, "ticks": int(ticks),
+                "all_reached_t_max": bool(all(x == pk.DONE for x in status)),
+                "p50_service_s": float(np.percentile(svc, 50)), "p99_service_s": float(np.percentile(svc, 99))}
+
+    def sequential(reqs, label):
+        t0 = time.perf_counter()
+        status = []
+        for p in reqs:
+            s = pk.Solver(p)
+            try:
+                st, _ = s.step(float("inf"))
+            except pk.DmfeError as e:
+                st = e.status
+            status.append(st)
+            s.close()
+            if len(status) % 16 == 0:
+                log(f"c4 {label}: {len(status)} of {len(reqs)} solved after {time.perf_counter() - t0:.0f} s")
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        log(f"c4 {label}: {len(reqs)} sequential solves in {wall:.1f} s ({len(reqs) / wall:.2f} solves/s)")
+        return {"solves": len(reqs), "wall_s": wall, "solves_per_s": len(reqs) / wall,
+                "all_reached_t_max": bool(all(x == pk.DONE for x in status))}
+
+    r32 = sweep_requests(pk, n, seed, pk.FP32_COMP, tmax_range)
+    r64 = sweep_requests(pk, n, seed, pk.FP64, tmax_range)
+    out["part"] = part
+    if part in ("all", "fp32"):
+        out.update(_c4_fp32(pk, torch, closed, r32, n, seed, arena))
+    if part in ("all", "fp64"):
+        out["fp64_closed"] = closed(r64, "fp64")
+        small = [k for k, p in enumerate(r64) if p.L <= 1024]
+        for name, reqs in (("fp64", r64), ("fp32c", r32)):
+            sub = [reqs[k] for k in small]
+            pooled = closed(sub, f"{name} small half pooled")
+            seq = sequential(sub, f"{name} small half sequential")
+            out[f"{name}_small_half"] = {"L": [512, 1024], "pooled": pooled, "sequential": seq,
+                                         "batching_gain": pooled["solves_per_s"] / seq["solves_per_s"]}
+    return out
+
+
+def _c4_fp32(pk, torch, closed, r32, n, seed, arena):
+    """FP32-comp closed batch, then Poisson arrivals at 0.8 x its capacity."""
+    import numpy as np
+    out = {}
+    out["fp32c_closed"] = closed(r32, "fp32c")
+    cap = out["fp32c_closed"]["solves_per_s"]
+    rng = np.random.default_rng(seed + 1)
+    arrivals = np.cumsum(rng.exponential(1.0 / (0.8 * cap), n))
+    pool = pk.Pool(arena, max_instances=256)
+    t0 = time.perf_counter()
+    nxt, tts, status = 0, [], []
+    t_log = t0
+    while len(tts) < n:
+        now = time.perf_counter() - t0
+        if time.perf_counter() - t_log > 20.0:
+            t_log = time.perf_counter()
+            log(f"c4 poisson: {len(tts)} of {n} done, {nxt} arrived after {now:.0f} s")
+        while nxt < n and arrivals[nxt] <= now:
+            pool.submit(r32[nxt])
+            nxt += 1
+        st = pool.run(20)
+        for rid in pool.poll():
+            _, tm = pool.result(rid)
+            tts.append(tm.total_s)
+            status.append(tm.status)
+            pool.release(rid)
+        if st.running == 0 and st.queued == 0 and nxt < n:
+            time.sleep(max(0.0, min(arrivals[nxt] - (time.perf_counter() - t0), 0.05)))
+    wall = time.perf_counter() - t0
+    pool.close()
+    tts = np.array(tts)
+    out["fp32c_poisson"] = {"arrival_rate_per_s": 0.8 * cap, "solves_per_s": n / wall, "wall_s": wall,
+                            "p50_time_to_solution_s": float(np.percentile(tts, 50)),
+                            "p99_time_to_solution_s": float(np.percentile(tts, 99)),
+                            "max_time_to_solution_s": float(tts.max()),
+                            "all_reached_t_max": bool(all(x == pk.DONE for x in status))}
+    log(f"c4 poisson: {n / wall:.2f} solves/s, p50 {out['fp32c_poisson']['p50_time_to_solution_s']:.2f} s, "
+        f"p99 {out['fp32c_poisson']['p99_time_to_solution_s']:.2f} s")
     return out
 
 
@@ -738,11 +860,20 @@ def main() -> int:
                     help="only the large-grid configuration: 16 solves at L=8192 in one pool")
     ap.add_argument("--stencils", action="store_true",
                     help="only the cost and accuracy of the theta-stencil schemes and the log-R option")
+    ap.add_argument("--c4", type=int, default=0,
+                    help="only the serving sweep with this many requests (pooled and one-by-one, both precisions)")
+    ap.add_argument("--c4-tmax", type=float, nargs=2, default=(1e2, 1e3), help="t_max range of --c4")
+    ap.add_argument("--c4-part", choices=["all", "fp32", "fp64"], default="all",
+                    help="--c4: fp32 = FP32-comp closed batch and Poisson arrivals; fp64 = FP64 closed batch and "
+                         "the pooled-against-sequential comparison on L in {512, 1024}")
     ap.add_argument("--c3-error", type=float, default=0.0,
                     help="only the FP32-comp error against FP64 on the L=4096 workload, both solved to this t")
     ap.add_argument("--fdt", action="store_true",
                     help="only the fluctuation-dissipation plot of pure p=3 at T=1/2 (chi against C) to t=1e4")
     ap.add_argument("--no-sparsify", action="store_true", help="skip the sparsification kernel's roofline line")
+    ap.add_argument("--no-long-window", action="store_true",
+                    help="skip the long window (for profiled runs: the value window is then the last "
+                         "launches of the history-integral kernel)")
     ap.add_argument("--sparsify", action="store_true",
                     help="only the sparsification residual kernel at L=4096, M=4096 (one pass, nothing removed)")
     ap.add_argument("--kernel-slices", type=int, default=2500,
@@ -773,6 +904,9 @@ def main() -> int:
         return 0
     if args.fdt:
         print(json.dumps(fdt_run(pk, torch)), flush=True)
+        return 0
+    if args.c4 > 0:
+        print(json.dumps(c4_sweep(pk, torch, args.c4, tuple(args.c4_tmax), part=args.c4_part)), flush=True)
         return 0
     if args.c3_error > 0:
         print(json.dumps(c3_fp32_error(pk, torch, args.c3_error)), flush=True)
@@ -807,8 +941,9 @@ def main() -> int:
                       "rhs_evals_per_step": o["config"]["rhs_evals_per_step"],
                       "hist_integral_avg_launch_us": o["roofline"]["avg_launch_us"],
                       "roofline": o["roofline"], "long_window": o["long_window"]}
-        out[other]["long_window_speedup_vs_" + prec_name] = (o["long_window"]["stage_evals_per_s"] /
-                                                            w["long_window"]["stage_evals_per_s"])
+        if w["long_window"] and o["long_window"]:
+            out[other]["long_window_speedup_vs_" + prec_name] = (o["long_window"]["stage_evals_per_s"] /
+                                                                w["long_window"]["stage_evals_per_s"])
     if not args.no_sparsify:
         out["sparsify_roofline"] = sparsify_bench(pk, torch)
     if not args.no_configs:
@@ -906,13 +1041,29 @@ def timed_window(pk, torch, prec_name: str, args) -> dict:
     t_flops = flops / (PEAK_FP64_TFLOPS * 1e12)
     alu = t_flops >= t_bytes
     log(f"window ({prec_name}): {steps} steps in {elapsed:.3f} s, hist_integral {avg_ms * 1e3:.1f} us/launch")
-    # the long window: three more sparsification passes
-    j0, j1, lsteps, lelapsed, lk = _kernel_window(pk, torch, s, passes=3, max_steps=12000, max_s=90.0)
-    lev = j1.rhs_evals - j0.rhs_evals
-    log(f"long window ({prec_name}): {lsteps} steps in {lelapsed:.2f} s, {j1.sparsify_calls - j0.sparsify_calls} "
-        f"sparsification passes, t {j0.t:.5g} -> {j1.t:.5g}, M {j0.M} -> {j1.M}")
-    s.close()
     scheme = lambda i: "SSPRK(10,4)" if i.scheme == pk.SCHEME_SSPRK104 else "DP5"
+    long_window = None
+    if not args.no_long_window:
+        # the long window: three more sparsification passes
+        j0, j1, lsteps, lelapsed, lk = _kernel_window(pk, torch, s, passes=3, max_steps=12000, max_s=90.0)
+        lev = j1.rhs_evals - j0.rhs_evals
+        log(f"long window ({prec_name}): {lsteps} steps in {lelapsed:.2f} s, "
+            f"{j1.sparsify_calls - j0.sparsify_calls} sparsification passes, t {j0.t:.5g} -> {j1.t:.5g}, "
+            f"M {j0.M} -> {j1.M}")
+        long_window = {
+            "what": "the steps after the value window until three more automatic sparsification passes, "
+                    "sparsification included",
+            "steps": int(lsteps), "seconds": lelapsed, "steps_per_s": lsteps / lelapsed,
+            "stage_evals_per_s": lev / lelapsed, "rhs_evals_per_step": lev / max(lsteps, 1),
+            "sparsify_passes": int(j1.sparsify_calls - j0.sparsify_calls),
+            "t_window": [j0.t, j1.t], "M_window": [int(j0.M), int(j1.M)], "scheme": scheme(j1),
+            "hist_integral_avg_launch_us": lk["hist_integral"][1] / max(lk["hist_integral"][0], 1) * 1e3,
+            "sparsify_avg_pass_us": lk["sparsify_residual"][1] / max(lk["sparsify_residual"][0], 1) * 1e3,
+            "kernel_s": {name: v[1] * 1e-3 for name, v in lk.items()},
+            "ssprk_regime": "not reached: at this capacity the run stays under DP5 (dt ~ 0.31 at t ~ 8000, "
+                            "where the 4096-slice history fills up and a pass frees nothing)",
+        }
+    s.close()
     return {
         "L": L,
         "steps": steps,
@@ -935,19 +1086,7 @@ def timed_window(pk, torch, prec_name: str, args) -> dict:
             "sparsify_passes_in_window": int(i1.sparsify_calls - i0.sparsify_calls),
             "kernel_ms_per_step": {name: v[1] / steps for name, v in k.items()},
         },
-        "long_window": {
-            "what": "the steps after the value window until three more automatic sparsification passes, "
-                    "sparsification included",
-            "steps": int(lsteps), "seconds": lelapsed, "steps_per_s": lsteps / lelapsed,
-            "stage_evals_per_s": lev / lelapsed, "rhs_evals_per_step": lev / max(lsteps, 1),
-            "sparsify_passes": int(j1.sparsify_calls - j0.sparsify_calls),
-            "t_window": [j0.t, j1.t], "M_window": [int(j0.M), int(j1.M)], "scheme": scheme(j1),
-            "hist_integral_avg_launch_us": lk["hist_integral"][1] / max(lk["hist_integral"][0], 1) * 1e3,
-            "sparsify_avg_pass_us": lk["sparsify_residual"][1] / max(lk["sparsify_residual"][0], 1) * 1e3,
-            "kernel_s": {name: v[1] * 1e-3 for name, v in lk.items()},
-            "ssprk_regime": "not reached: at this capacity the run stays under DP5 (dt ~ 0.31 at t ~ 8000, "
-                            "where the 4096-slice history fills up and a pass frees nothing)",
-        },
+        "long_window": long_window,
         "roofline": {
             "kernel": "hist_integral",
             "bound": "alu" if alu else "hbm",

@@ -108,3 +108,30 @@ def test_fdt_approached_above_the_dynamical_transition():
     s.close()
     assert all(dev[400.0, tau] < 5e-3 for tau in (0.5, 1.0, 2.0, 5.0))
     assert dev[400.0, 5.0] < dev[100.0, 5.0] / 3
+
+
+def test_fluctuation_dissipation_plot_of_pure_p3():
+    """Sec. 4.3 (Fig. RvsC): pure p = 3 with f = q^3 quenched to T = 1/2.  On the newest
+    stored slice chi(t, s) = int_s^t R(t, tau) dtau against C(t, s) has slope 1/T = 2
+    for C above q_EA = 0.766911 (FDT), and a smaller slope below it that grows
+    towards x_th = 0.607865 with the age t; the break of the curve lies just below
+    q_EA and moves up with t."""
+    import bench
+    p = pk.make_params({3: 2.0}, 0.5, t_max=1e7, L=256, M_cap=8192, eps=1e-8, dt0=1e-3, dt_min=1e-14)
+    s = pk.Solver(p)
+    th = s.read(pk.F_THETA)
+    fits = []
+    for tp in (30.0, 100.0):
+        _, info = s.step(tp)
+        M = int(info.M)
+        C, R = s.read(pk.F_C, M - 1, 1)[0], s.read(pk.F_R, M - 1, 1)[0]
+        tn = float(s.read(pk.F_T_GRID, M - 1, 1)[0])
+        chi, Cc = bench.fdt_chi_vs_c(th, C, R, tn)
+        fits.append(bench.fdt_slopes(chi, Cc, 0.766911))
+        say(f"  t={tn:.4g}: {fits[-1]}")
+    s.close()
+    for f in fits:
+        assert abs(f["fdt_slope"] - 2.0) < 0.02
+        assert 0.3 < f["aging_slope"] < 0.607865
+        assert 0.74 < f["break_C"] < 0.766911
+    assert fits[1]["aging_slope"] > fits[0]["aging_slope"] and fits[1]["break_C"] > fits[0]["break_C"]

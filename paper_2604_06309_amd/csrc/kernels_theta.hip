@@ -143,6 +143,23 @@ __device__ __forceinline__ void interp2(const YPoint* row, int base, const doubl
         r = fma(w[k], v.r, r);
     }
 }
+// The same sums with all S reads issued before the first product (the scheduler
+// otherwise waits on each read in turn); the sums are formed in the same order.
+template <int S>
+__device__ __forceinline__ void interp2_batched(const YPoint* row, int base, const double (&w)[S], double& c,
+                                                double& r) {
+    YPoint v[S];
+#pragma unroll
+    for (int k = 0; k < S; ++k) v[k] = row[base + k];
+    __builtin_amdgcn_sched_barrier(0);
+    c = 0.0;
+    r = 0.0;
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+        c = fma(w[k], v[k].c, c);
+        r = fma(w[k], v[k].r, r);
+    }
+}
 template <int S, class HP, class R = hreal_t<HP>>
 __device__ __forceinline__ void interp4(const HP* row, int base, const R (&w)[S], R& c, R& r, R& dc, R& dr) {
     c = r = dc = dr = R(0);
@@ -153,6 +170,86 @@ __device__ __forceinline__ void interp4(const HP* row, int base, const R (&w)[S]
         r = fma(w[k], v.r, r);
         dc = fma(w[k], v.dc, dc);
         dr = fma(w[k], v.dr, dr);
+    }
+}
+
+// Nodes per slot of a wave's shared-node buffer (below): 28 keeps a block's LDS
+// within 160 KB with the times of 16384 slices beside it.
+constexpr int kTileNodes = 28;
+
+// The 2-D stencil of one target on two FP64 slots, read in batches of 5 points
+// (10 loads in flight per lane before the first product), sums in the order of
+// interp4.
+template <int S>
+__device__ __forceinline__ void gathered_stencil(const HPoint* p0, const HPoint* p1, int base, const double (&w)[S],
+                                                 double& c0, double& r0, double& dc0, double& dr0, double& c1,
+                                                 double& r1, double& dc1, double& dr1) {
+    constexpr int B = 5;
+    c0 = r0 = dc0 = dr0 = c1 = r1 = dc1 = dr1 = 0.0;
+#pragma unroll
+    for (int kb = 0; kb < 2 * S; kb += B) {
+        HPoint v[B];
+#pragma unroll
+        for (int q = 0; q < B; ++q) {
+            const int k = kb + q;
+            if (k < 2 * S) v[q] = k < S ? p0[base + k] : p1[base + k - S];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int q = 0; q < B; ++q) {
+            const int k = kb + q;
+            if (k < S) {
+                c0 = fma(w[k], v[q].c, c0);
+                r0 = fma(w[k], v[q].r, r0);
+                dc0 = fma(w[k], v[q].dc, dc0);
+                dr0 = fma(w[k], v[q].dr, dr0);
+            } else if (k < 2 * S) {
+                c1 = fma(w[k - S], v[q].c, c1);
+                r1 = fma(w[k - S], v[q].r, r1);
+                dc1 = fma(w[k - S], v[q].dc, dc1);
+                dr1 = fma(w[k - S], v[q].dr, dr1);
+            }
+        }
+    }
+}
+// The same from a wave's LDS buffer: the first slot's nodes at [0, kTileNodes), the
+// second's at [kTileNodes, 2 kTileNodes), this stencil at offset off in each.
+template <int S, class LP>
+__device__ __forceinline__ void shared_stencil(const LP* tile, int off, const double (&w)[S], double& c0,
+                                               double& r0, double& dc0, double& dr0, double& c1, double& r1,
+                                               double& dc1, double& dr1) {
+    constexpr int B = 5;
+    c0 = r0 = dc0 = dr0 = c1 = r1 = dc1 = dr1 = 0.0;
+#pragma unroll
+    for (int kb = 0; kb < 2 * S; kb += B) {
+        double vc[B], vr[B], vdc[B], vdr[B];
+#pragma unroll
+        for (int q = 0; q < B; ++q) {
+            const int k = kb + q;
+            if (k < 2 * S) {
+                const int id = k < S ? off + k : kTileNodes + off + k - S;
+                vc[q] = tile[id].c;
+                vr[q] = tile[id].r;
+                vdc[q] = tile[id].dc;
+                vdr[q] = tile[id].dr;
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int q = 0; q < B; ++q) {
+            const int k = kb + q;
+            if (k < S) {
+                c0 = fma(w[k], vc[q], c0);
+                r0 = fma(w[k], vr[q], r0);
+                dc0 = fma(w[k], vdc[q], dc0);
+                dr0 = fma(w[k], vdr[q], dr0);
+            } else if (k < 2 * S) {
+                c1 = fma(w[k - S], vc[q], c1);
+                r1 = fma(w[k - S], vr[q], r1);
+                dc1 = fma(w[k - S], vdc[q], dc1);
+                dr1 = fma(w[k - S], vdr[q], dr1);
+            }
+        }
     }
 }
 
@@ -392,10 +489,22 @@ __host__ __device__ inline size_t lds_offset_y(int nb) {
 __host__ __device__ inline size_t lds_offset_red(int nb, int L, bool yl) {
     return lds_offset_y(nb) + (yl ? size_t(L) * 16 : 0);
 }
+// Shared 2-D stencil nodes (FP64 history, default stencil): a wave whose 64 targets
+// bracket the same pair of slots and whose stencils lie within kTileNodes
+// consecutive nodes reads those nodes of both slots once, one point per lane, into
+// a buffer of its own in LDS (2 x kTileNodes points), and its stencils then read
+// LDS instead of gathering from global memory.
+template <class HP, int VAR> constexpr bool shared_nodes() { return VAR == 0 && sizeof(HP) == sizeof(HPoint); }
 template <class HP, int VAR = 0>
-__host__ __device__ inline size_t lds_bytes(int nb, int L, bool yl) {
+__host__ __device__ inline size_t lds_offset_tile(int nb, int L, bool yl) {
     constexpr int ph = HistCfg<HP, VAR>::phases;
     return lds_offset_red(nb, L, yl) + (ph > 1 ? size_t(kRowsPerBlock) * ph * 9 * 8 : 0);
+}
+template <class HP, int VAR = 0>
+__host__ __device__ inline size_t lds_bytes(int nb, int L, bool yl) {
+    constexpr int waves = kGroups * HistCfg<HP, VAR>::phases;
+    return lds_offset_tile<HP, VAR>(nb, L, yl) +
+           (shared_nodes<HP, VAR>() ? size_t(waves) * 2 * kTileNodes * sizeof(HP) : 0);
 }
 
 template <int S, int PM, class HP, bool YL, int VAR, bool TG = false>
@@ -507,6 +616,13 @@ __device__ __forceinline__ void hist_integral_block(const StageArgs& a, int row_
     const LogPoint* lstage = use_log ? a.lstage : nullptr;
     const LogPoint* lc0 = use_log ? mirror(c0p) : nullptr;
     const LogPoint* lc1 = use_log ? mirror(c1p) : nullptr;
+    constexpr bool kShared = shared_nodes<HP, VAR>();
+    using lds_hp = HP __attribute__((address_space(3)));
+    // (an address-space cast: the generic pointer to the dynamic LDS becomes an LDS pointer)
+    lds_hp* const tile = kShared ? (lds_hp*)(reinterpret_cast<HP*>(reinterpret_cast<char*>(smem) +
+                                                                   lds_offset_tile<HP, VAR>(nbl, L, YL))) +
+                                       wave * 2 * kTileNodes
+                                 : nullptr;
     const double* Xa = a.X + size_t(j) * L;          // row j, read forwards
     const double* Xb = a.X + size_t(L - 1 - j) * L;  // row L-1-j, read backwards
     const double* Xdj = a.Xd + size_t(j) * L;
@@ -532,7 +648,8 @@ __device__ __forceinline__ void hist_integral_block(const StageArgs& a, int row_
                     if constexpr (use_log) aR = log_interp_stage<S>(lstage, base, wl, aR);
                 } else {
                     const int base = lagrange<S>(xa, L, wl);
-                    interp2<S>(ysrc, base, wl, aC, aR);
+                    if constexpr (kShared) interp2_batched<S>(ysrc, base, wl, aC, aR);
+                    else interp2<S>(ysrc, base, wl, aC, aR);
                 }
             }
             // b: (t, phi)
@@ -544,7 +661,8 @@ __device__ __forceinline__ void hist_integral_block(const StageArgs& a, int row_
                     if constexpr (use_log) bR = log_interp_stage<S>(lstage, base, wl, bR);
                 } else {
                     const int base = lagrange<S>(double(L - 1) - xb, L, wl);
-                    interp2<S>(ysrc, base, wl, bC, bR);
+                    if constexpr (kShared) interp2_batched<S>(ysrc, base, wl, bC, bR);
+                    else interp2<S>(ysrc, base, wl, bC, bR);
                 }
             }
             // c: (t', theta_i)
@@ -581,6 +699,7 @@ __device__ __forceinline__ void hist_integral_block(const StageArgs& a, int row_
                 const HP* p0;
                 const HP* p1;
                 double h00, h10, h01, h11;
+                int key = -2;  // the slot pair: bracket m, -1 inside the current step, -2 otherwise
                 if (nb >= 2 && s <= tb) {
                     int m;
                     if constexpr (sizeof(HS) == 4) {
@@ -602,6 +721,7 @@ __device__ __forceinline__ void hist_integral_block(const StageArgs& a, int row_
                     h11 = (u * u * u - u * u) * h;
                     p0 = hist + size_t(a.slot[m]) * L;
                     p1 = hist + size_t(a.slot[m + 1]) * L;
+                    key = m;
                 } else if (nb >= 1 && s > tb) {
                     const double u = (s - tb) / hq;
                     h00 = 1.0 - u * u;
@@ -610,6 +730,7 @@ __device__ __forceinline__ void hist_integral_block(const StageArgs& a, int row_
                     h11 = h01;
                     p0 = bslot;
                     p1 = stage;
+                    key = -1;
                 } else if (nb == 0) {
                     h00 = 1.0, h10 = 1.0, h01 = 0.0, h11 = 0.0;
                     p0 = p1 = stage;
@@ -618,11 +739,43 @@ __device__ __forceinline__ void hist_integral_block(const StageArgs& a, int row_
                     p0 = p1 = slot0;
                 }
                 double c0, r0, dc0, dr0, c1, r1, dc1, dr1;
-                interp4<S>(p0, base, wd, c0, r0, dc0, dr0);
-                // FP32 storage: values are widened as they arrive, so the second slot's
-                // gathers wait for the first (keeps the widened values within registers)
-                if constexpr (sizeof(HS) == 4) __builtin_amdgcn_sched_barrier(0);
-                interp4<S>(p1, base, wd, c1, r1, dc1, dr1);
+                if constexpr (kShared) {
+                    // Every lane active (a ragged last tile is not), one slot pair for the whole
+                    // wave, and every stencil within kTileNodes nodes of lane 7's, the smallest
+                    // base of the tile (psi falls with theta_i and rises with theta_j).
+                    const int k0 = __builtin_amdgcn_readfirstlane(key);
+                    const int bmin = __builtin_amdgcn_readlane(base, kColsPerWave - 1);
+                    const int off = base - bmin;
+                    const bool ok = key == k0 && off >= 0 && off <= kTileNodes - S;
+                    if (__builtin_amdgcn_ballot_w64(true) == ~0ull && __builtin_amdgcn_ballot_w64(!ok) == 0) {
+                        // lane q < kTileNodes reads node bmin + q of the first slot, lane
+                        // kTileNodes + q the same node of the second; the lanes above 2 kTileNodes idle
+                        if (lane < 2 * kTileNodes) {
+                            const bool second = lane >= kTileNodes;
+                            const int q = second ? lane - kTileNodes : lane;
+                            const HP* src = second ? p1 : p0;
+                            const HP v = src[bmin + q < L ? bmin + q : L - 1];
+                            tile[lane].c = v.c;
+                            tile[lane].r = v.r;
+                            tile[lane].dc = v.dc;
+                            tile[lane].dr = v.dr;
+                        }
+                        // LDS operations of one wave take effect in program order: the fences
+                        // only keep the compiler from moving the reads above the writes
+                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                        __builtin_amdgcn_wave_barrier();
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                        shared_stencil<S>(tile, off, wd, c0, r0, dc0, dr0, c1, r1, dc1, dr1);
+                    } else {
+                        gathered_stencil<S>(p0, p1, base, wd, c0, r0, dc0, dr0, c1, r1, dc1, dr1);
+                    }
+                } else {
+                    interp4<S>(p0, base, wd, c0, r0, dc0, dr0);
+                    // FP32 storage: values are widened as they arrive, so the second slot's
+                    // gathers wait for the first (keeps the widened values within registers)
+                    if constexpr (sizeof(HS) == 4) __builtin_amdgcn_sched_barrier(0);
+                    interp4<S>(p1, base, wd, c1, r1, dc1, dr1);
+                }
                 dC = h00 * c0 + h10 * dc0 + h01 * c1 + h11 * dc1;
                 dR = h00 * r0 + h10 * dr0 + h01 * r1 + h11 * dr1;
                 if constexpr (use_log) {

@@ -342,6 +342,62 @@ def c4_sweep(pk, torch, n: int = 128, tmax_range=(1e2, 1e3), seed: int = 2026040
     return out
 
 
+def pool_ticks(pk, torch, Ls=(512, 1024), ns=(1, 4, 16, 64, 128), ticks: int = 300, solo: bool = True) -> dict:
+    """Cost of one serving tick against the number of admitted solves (FP64, 2+3+4 model,
+    a_p^2 = 0.3, 0.4, 0.3, T = 0.8, history cap L, eps = 1e-6): wall time per tick (one RK
+    stage of every solve: the batched launches, the descriptor upload, one synchronisation
+    and the host controller) and per stage evaluation, after 120 untimed ticks; beside it
+    one solve stepped alone (wall and kernel time per stage, from the library's HIP
+    events).  Under rocprofv3 --kernel-trace, a run restricted to one L and one count
+    (which skips the solve alone) gives the GPU time per tick; the rest of the wall time
+    is the host's."""
+    out = {"ticks": ticks, "rows": []}
+    for L in Ls:
+        p = pk.make_params({2: 0.3, 3: 0.4, 4: 0.3}, 0.8, t_max=1e6, L=L, M_cap=L, eps=1e-6, dt0=1e-3, dt_min=1e-12)
+        if not solo:
+            solo_row = {"L": L, "solo_wall_us_per_stage": None, "solo_kernel_us_per_stage": None}
+        else:
+            solo_row = _solo_stage_cost(pk, torch, p)
+            log(f"pool ticks L={L}: one solve alone {solo_row['solo_wall_us_per_stage']:.1f} us per stage")
+        for n in ns:
+            pool = pk.Pool(n * pk.dmfe_footprint(p) + (1 << 20), max_instances=max(n, 1))
+            for _ in range(n):
+                pool.submit(p)
+            pool.run(120)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = pool.run(ticks)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            pool.close()
+            row = {**solo_row, "instances": n, "us_per_tick": wall / ticks * 1e6,
+                   "us_per_stage_eval": wall / ticks / n * 1e6, "running_at_end": int(st.running)}
+            if solo:
+                row["pooled_vs_alone_per_stage"] = solo_row["solo_wall_us_per_stage"] / row["us_per_stage_eval"]
+            out["rows"].append(row)
+            log(f"pool ticks L={L} n={n}: {row['us_per_tick']:.1f} us per tick, {row['us_per_stage_eval']:.2f} us "
+                f"per stage evaluation")
+    return out
+
+
+def _solo_stage_cost(pk, torch, p) -> dict:
+    """Wall and kernel time per RK stage of one solve stepped alone (100 steps after 100)."""
+    s = pk.Solver(p)
+    s.step(float("inf"), 100)
+    s.timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(float("inf"), 100)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    k = {name: s.timing_read(kid) for name, kid in (("hist_integral", pk.K_HIST_INTEGRAL),
+                                                   ("stage_prep", pk.K_STAGE_PREP), ("rk", pk.K_RK))}
+    evals = int(k["hist_integral"][0])
+    s.close()
+    return {"L": p.L, "solo_wall_us_per_stage": wall / evals * 1e6,
+            "solo_kernel_us_per_stage": {n: v[1] / max(v[0], 1) * 1e3 for n, v in k.items()}}
+
+
 def _c4_fp32(pk, torch, closed, r32, n, seed, arena):
     """FP32-comp closed batch, then Poisson arrivals at 0.8 x its capacity."""
     import numpy as np
@@ -871,6 +927,10 @@ def main() -> int:
     ap.add_argument("--fdt", action="store_true",
                     help="only the fluctuation-dissipation plot of pure p=3 at T=1/2 (chi against C) to t=1e4")
     ap.add_argument("--no-sparsify", action="store_true", help="skip the sparsification kernel's roofline line")
+    ap.add_argument("--pool-ticks", action="store_true",
+                    help="serving tick cost against the number of admitted solves (FP64, L=512 and 1024)")
+    ap.add_argument("--pool-L", type=int, default=0, help="restrict --pool-ticks to one grid length")
+    ap.add_argument("--pool-n", type=int, default=0, help="restrict --pool-ticks to one number of solves")
     ap.add_argument("--no-long-window", action="store_true",
                     help="skip the long window (for profiled runs: the value window is then the last "
                          "launches of the history-integral kernel)")
@@ -904,6 +964,11 @@ def main() -> int:
         return 0
     if args.fdt:
         print(json.dumps(fdt_run(pk, torch)), flush=True)
+        return 0
+    if args.pool_ticks:
+        Ls = (args.pool_L,) if args.pool_L else (512, 1024)
+        ns = (args.pool_n,) if args.pool_n else (1, 4, 16, 64, 128)
+        print(json.dumps(pool_ticks(pk, torch, Ls, ns, solo=not args.pool_n)), flush=True)
         return 0
     if args.c4 > 0:
         print(json.dumps(c4_sweep(pk, torch, args.c4, tuple(args.c4_tmax), part=args.c4_part)), flush=True)

@@ -458,9 +458,8 @@ dmfe_status step_stage(dmfe_handle* h) {
     YPoint* kst = kb + size_t(st) * L;
     const double tst = c.tn + T.c[st] * c.dt;
     if (st == 0) {
-        if (h->fsal_valid) {
-            HCHK(hipMemcpyAsync(kst, kb + size_t(6) * L, sizeof(YPoint) * L, hipMemcpyDeviceToDevice, h->stream));
-        } else {
+        // first-same-as-last: k_0 already holds the last step's final stage (written on accept)
+        if (!h->fsal_valid) {
             const dmfe_status s = eval_rhs(h, tst, c.M - 1, y0, kst, slot_ptr(h, h->slot[c.M - 1]));
             if (s != DMFE_OK) return s;
         }
@@ -512,21 +511,28 @@ dmfe_status step_decide(dmfe_handle* h, double err) {
         const int slot = c.next_slot;
         h->free_slots.pop_back();
         LogPoint* lm = log_mirror(h);
-        HCHK(launch_append(L, h->at<YPoint>(h->lo.ynew), slot_ptr(h, slot), h->fp32,
-                           lm ? lm + size_t(slot) * L : nullptr, h->stream));
         h->thist.push_back(tn + dt);
         h->slot.push_back(slot);
         h->M = M + 1;
         h->nb_valid = T.fsal ? h->M : M;
         h->t = tn + dt;
-        // ynew becomes the state; the new slice's time and slot go to the device index arrays
-        HCHK(hipMemcpyAsync(y0, h->at<YPoint>(h->lo.ynew), sizeof(YPoint) * L, hipMemcpyDeviceToDevice, h->stream));
-        double* stage = h->pinned + 8 + 2 * (h->accepted & 1);  // alternating staging cells
-        stage[0] = h->t;
-        std::memcpy(&stage[1], &slot, sizeof(int));
-        HCHK(hipMemcpyAsync(h->at<double>(h->lo.thist) + M, &stage[0], sizeof(double), hipMemcpyHostToDevice,
-                            h->stream));
-        HCHK(hipMemcpyAsync(h->at<int>(h->lo.slot) + M, &stage[1], sizeof(int), hipMemcpyHostToDevice, h->stream));
+        // one launch: the new slice, the new state, the next step's first stage, and the new
+        // slice's time and slot in the device index arrays
+        YPoint* kb = h->at<YPoint>(h->lo.k);
+        AcceptArgs aa{};
+        aa.L = L;
+        aa.M = M;
+        aa.slot_new = slot;
+        aa.t_new = h->t;
+        aa.ynew = h->at<YPoint>(h->lo.ynew);
+        aa.slot_dst = slot_ptr(h, slot);
+        aa.lslot = lm ? lm + size_t(slot) * L : nullptr;
+        aa.y0 = y0;
+        aa.k_last = T.fsal ? kb + size_t(T.S - 1) * L : nullptr;
+        aa.k_first = T.fsal ? kb : nullptr;
+        aa.thist = h->at<double>(h->lo.thist);
+        aa.slots = h->at<int>(h->lo.slot);
+        HCHK(launch_accept(aa, h->fp32, h->stream));
         h->fsal_valid = T.fsal;
         h->accepted += 1;
     } else {

@@ -237,6 +237,10 @@ dmfe_status dmfe_checkpoint_load(const char* path, const dmfe_resources* res, dm
     if ((e = hipMemcpyAsync(h->at<YPoint>(h->lo.k) + size_t(6) * L, q, yb, hipMemcpyHostToDevice, h->stream)) !=
         hipSuccess)
         return bail(fail(e, "hipMemcpyAsync"));
+    // the next step's first stage reads it from k_0 (first-same-as-last)
+    if (h->fsal_valid &&
+        (e = hipMemcpyAsync(h->at<YPoint>(h->lo.k), q, yb, hipMemcpyHostToDevice, h->stream)) != hipSuccess)
+        return bail(fail(e, "hipMemcpyAsync"));
     q += yb;
     // slots 0..M-1 are contiguous at the start of the history
     if ((e = hipMemcpyAsync(slot_ptr(h, 0), q, size_t(M) * L * pb, hipMemcpyHostToDevice, h->stream)) != hipSuccess)

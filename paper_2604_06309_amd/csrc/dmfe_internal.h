@@ -102,7 +102,22 @@ hipError_t launch_rk_combine(int L, const YPoint* y0, const YPoint* k, int nk, c
 hipError_t launch_rk_finish(int L, const YPoint* y0, const YPoint* k, int nk, const double* b, const double* e,
                             double dt, YPoint* ynew, double* eps_out, hipStream_t st);
 // History pointers below are HPoint* when fp32 == 0 and HPoint32* when fp32 == 1.
-hipError_t launch_append(int L, const YPoint* y, void* slot_dst, int fp32, LogPoint* lslot, hipStream_t st);
+// Accepting a step: y_new into slot_dst (as (C, R)) and into y0; k_last -> k_first when
+// k_first is set (first-same-as-last); t_new and slot_new at index M of the device
+// time and slot arrays; the slot's log mirror when lslot is set.
+struct AcceptArgs {
+    int L, M, slot_new;
+    double t_new;
+    const YPoint* ynew;
+    void* slot_dst;
+    LogPoint* lslot;
+    YPoint* y0;
+    const YPoint* k_last;
+    YPoint* k_first;
+    double* thist;
+    int* slots;
+};
+hipError_t launch_accept(const AcceptArgs& a, int fp32, hipStream_t st);
 // the log mirror of `count` stored slices (log-R option) from their stored values
 hipError_t launch_log_mirror(int L, int count, const int* slot, const void* hist, int fp32, LogPoint* lhist,
                              hipStream_t st);

@@ -177,18 +177,18 @@ __device__ __forceinline__ void interp4(const HP* row, int base, const R (&w)[S]
 // within 160 KB with the times of 16384 slices beside it.
 constexpr int kTileNodes = 28;
 
-// The 2-D stencil of one target on two FP64 slots, read in batches of 5 points
-// (10 loads in flight per lane before the first product), sums in the order of
-// interp4.
-template <int S>
-__device__ __forceinline__ void gathered_stencil(const HPoint* p0, const HPoint* p1, int base, const double (&w)[S],
+// The 2-D stencil of one target on two slots, read in batches of 5 points (10 loads
+// in flight per lane before the first product), values widened to FP64 as they are
+// used, sums in the order of interp4.
+template <int S, class HP>
+__device__ __forceinline__ void gathered_stencil(const HP* p0, const HP* p1, int base, const double (&w)[S],
                                                  double& c0, double& r0, double& dc0, double& dr0, double& c1,
                                                  double& r1, double& dc1, double& dr1) {
     constexpr int B = 5;
     c0 = r0 = dc0 = dr0 = c1 = r1 = dc1 = dr1 = 0.0;
 #pragma unroll
     for (int kb = 0; kb < 2 * S; kb += B) {
-        HPoint v[B];
+        HP v[B];
 #pragma unroll
         for (int q = 0; q < B; ++q) {
             const int k = kb + q;
@@ -199,15 +199,15 @@ __device__ __forceinline__ void gathered_stencil(const HPoint* p0, const HPoint*
         for (int q = 0; q < B; ++q) {
             const int k = kb + q;
             if (k < S) {
-                c0 = fma(w[k], v[q].c, c0);
-                r0 = fma(w[k], v[q].r, r0);
-                dc0 = fma(w[k], v[q].dc, dc0);
-                dr0 = fma(w[k], v[q].dr, dr0);
+                c0 = fma(w[k], double(v[q].c), c0);
+                r0 = fma(w[k], double(v[q].r), r0);
+                dc0 = fma(w[k], double(v[q].dc), dc0);
+                dr0 = fma(w[k], double(v[q].dr), dr0);
             } else if (k < 2 * S) {
-                c1 = fma(w[k - S], v[q].c, c1);
-                r1 = fma(w[k - S], v[q].r, r1);
-                dc1 = fma(w[k - S], v[q].dc, dc1);
-                dr1 = fma(w[k - S], v[q].dr, dr1);
+                c1 = fma(w[k - S], double(v[q].c), c1);
+                r1 = fma(w[k - S], double(v[q].r), r1);
+                dc1 = fma(w[k - S], double(v[q].dc), dc1);
+                dr1 = fma(w[k - S], double(v[q].dr), dr1);
             }
         }
     }
@@ -447,10 +447,10 @@ constexpr int kGroups = kRowsPerBlock / kRowsPerWave;  // row groups of a block
 
 
 // Tile configuration per history storage type, chosen by measurement at the
-// L = 4096 workload.  FP64: 12 waves per block (3 per SIMD, 125 VGPRs) with the
-// 2-D stencil issued first in the iteration, so its gathers overlap the
-// stage-slice stencils; FP32: 8 waves per block with the stage-slice stencils
-// first.
+// L = 4096 workload: 12 waves per block (3 per SIMD) with the 2-D stencil issued
+// first in the iteration, so its reads overlap the stage-slice stencils, for both
+// history precisions (with the shared-node tiles below the FP32 kernel fits 3 waves
+// per SIMD; before them it ran 8 waves per block, stage-slice stencils first).
 template <class HP, int VAR = 0> struct HistCfg {
     // The other theta schemes and the log-R option hold more values per pair:
     // fewer waves per block leave each wave the registers to do so without
@@ -465,8 +465,8 @@ template <> struct HistCfg<HPoint, 0> {
     static constexpr bool d_first = true;
 };
 template <> struct HistCfg<HPoint32, 0> {
-    static constexpr int phases = 8;
-    static constexpr bool d_first = false;
+    static constexpr int phases = 12;
+    static constexpr bool d_first = true;
 };
 template <class HP, int VAR = 0> constexpr int hist_threads() { return kGroups * HistCfg<HP, VAR>::phases * kWave; }
 
@@ -489,12 +489,12 @@ __host__ __device__ inline size_t lds_offset_y(int nb) {
 __host__ __device__ inline size_t lds_offset_red(int nb, int L, bool yl) {
     return lds_offset_y(nb) + (yl ? size_t(L) * 16 : 0);
 }
-// Shared 2-D stencil nodes (FP64 history, default stencil): a wave whose 64 targets
-// bracket the same pair of slots and whose stencils lie within kTileNodes
-// consecutive nodes reads those nodes of both slots once, one point per lane, into
-// a buffer of its own in LDS (2 x kTileNodes points), and its stencils then read
-// LDS instead of gathering from global memory.
-template <class HP, int VAR> constexpr bool shared_nodes() { return VAR == 0 && sizeof(HP) == sizeof(HPoint); }
+// Shared 2-D stencil nodes (default stencil): a wave whose 64 targets bracket the
+// same pair of slots and whose stencils lie within kTileNodes consecutive nodes
+// reads those nodes of both slots once, one point per lane, into a buffer of its
+// own in LDS (2 x kTileNodes points, widened to FP64 for an FP32 history), and its
+// stencils then read LDS instead of gathering from global memory.
+template <class HP, int VAR> constexpr bool shared_nodes() { return VAR == 0; }
 template <class HP, int VAR = 0>
 __host__ __device__ inline size_t lds_offset_tile(int nb, int L, bool yl) {
     constexpr int ph = HistCfg<HP, VAR>::phases;
@@ -504,7 +504,7 @@ template <class HP, int VAR = 0>
 __host__ __device__ inline size_t lds_bytes(int nb, int L, bool yl) {
     constexpr int waves = kGroups * HistCfg<HP, VAR>::phases;
     return lds_offset_tile<HP, VAR>(nb, L, yl) +
-           (shared_nodes<HP, VAR>() ? size_t(waves) * 2 * kTileNodes * sizeof(HP) : 0);
+           (shared_nodes<HP, VAR>() ? size_t(waves) * 2 * kTileNodes * sizeof(HPoint) : 0);
 }
 
 template <int S, int PM, class HP, bool YL, int VAR, bool TG = false>
@@ -617,9 +617,9 @@ __device__ __forceinline__ void hist_integral_block(const StageArgs& a, int row_
     const LogPoint* lc0 = use_log ? mirror(c0p) : nullptr;
     const LogPoint* lc1 = use_log ? mirror(c1p) : nullptr;
     constexpr bool kShared = shared_nodes<HP, VAR>();
-    using lds_hp = HP __attribute__((address_space(3)));
+    using lds_hp = HPoint __attribute__((address_space(3)));
     // (an address-space cast: the generic pointer to the dynamic LDS becomes an LDS pointer)
-    lds_hp* const tile = kShared ? (lds_hp*)(reinterpret_cast<HP*>(reinterpret_cast<char*>(smem) +
+    lds_hp* const tile = kShared ? (lds_hp*)(reinterpret_cast<HPoint*>(reinterpret_cast<char*>(smem) +
                                                                    lds_offset_tile<HP, VAR>(nbl, L, YL))) +
                                        wave * 2 * kTileNodes
                                  : nullptr;
@@ -755,10 +755,10 @@ __device__ __forceinline__ void hist_integral_block(const StageArgs& a, int row_
                             const int q = second ? lane - kTileNodes : lane;
                             const HP* src = second ? p1 : p0;
                             const HP v = src[bmin + q < L ? bmin + q : L - 1];
-                            tile[lane].c = v.c;
-                            tile[lane].r = v.r;
-                            tile[lane].dc = v.dc;
-                            tile[lane].dr = v.dr;
+                            tile[lane].c = double(v.c);
+                            tile[lane].r = double(v.r);
+                            tile[lane].dc = double(v.dc);
+                            tile[lane].dr = double(v.dr);
                         }
                         // LDS operations of one wave take effect in program order: the fences
                         // only keep the compiler from moving the reads above the writes
@@ -958,16 +958,29 @@ __global__ __launch_bounds__(1024) void k_rk_finish_multi(const FinishDesc* __re
     rk_finish_body(q.L, q.y0, q.k, q.nk, q.b, q.e, q.dt, q.ynew, q.eps);
 }
 
+// Accepting a step (Sec. 3.2): the new state goes into its slice slot as (C, R) (the
+// derivative half is written by a first-same-as-last scheme's last stage, else by
+// the next step's first stage) and becomes the state; with a first-same-as-last
+// scheme the last stage's derivative becomes the next step's first; thread 0 writes
+// the slice's time and slot to the device copies of the ordered history.
 template <class HP>
-__global__ void k_append(int L, const YPoint* __restrict__ y, HP* __restrict__ dst, LogPoint* __restrict__ lm) {
+__global__ void k_accept(const AcceptArgs a) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= L) return;
-    const hreal_t<HP> r = hreal_t<HP>(y[i].r);
-    dst[i].c = hreal_t<HP>(y[i].c);
+    if (i == 0) {
+        a.thist[a.M] = a.t_new;
+        a.slots[a.M] = a.slot_new;
+    }
+    if (i >= a.L) return;
+    HP* dst = static_cast<HP*>(a.slot_dst);
+    const YPoint v = a.ynew[i];
+    const hreal_t<HP> r = hreal_t<HP>(v.r);
+    dst[i].c = hreal_t<HP>(v.c);
     dst[i].r = r;
+    a.y0[i] = v;
+    if (a.k_first) a.k_first[i] = a.k_last[i];
     // log mirror from the stored values; dr is the derivative a first-same-as-last
     // stage stored already, else a placeholder the next first stage overwrites
-    if (lm) lm[i] = log_point(double(r), double(dst[i].dr));
+    if (a.lslot) a.lslot[i] = log_point(double(r), double(dst[i].dr));
 }
 
 template <class HP>
@@ -1339,13 +1352,11 @@ hipError_t launch_rk_finish(int L, const YPoint* y0, const YPoint* k, int nk, co
     return hipGetLastError();
 }
 
-hipError_t launch_append(int L, const YPoint* y, void* slot_dst, int fp32, LogPoint* lslot, hipStream_t st) {
+hipError_t launch_accept(const AcceptArgs& a, int fp32, hipStream_t st) {
     if (fp32)
-        hipLaunchKernelGGL(k_append<HPoint32>, dim3(nblk(L, 256)), dim3(256), 0, st, L, y,
-                           static_cast<HPoint32*>(slot_dst), lslot);
+        hipLaunchKernelGGL(k_accept<HPoint32>, dim3(nblk(a.L, 256)), dim3(256), 0, st, a);
     else
-        hipLaunchKernelGGL(k_append<HPoint>, dim3(nblk(L, 256)), dim3(256), 0, st, L, y, static_cast<HPoint*>(slot_dst),
-                           lslot);
+        hipLaunchKernelGGL(k_accept<HPoint>, dim3(nblk(a.L, 256)), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

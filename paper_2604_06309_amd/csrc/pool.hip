@@ -213,7 +213,7 @@ dmfe_status tick(dmfe_pool* P) {
         const double tst = c.tn + T.c[st] * c.dt;
         if (fp32 < 0) fp32 = h->fp32;
         if (st == 0 && h->fsal_valid) {
-            HCHK(hipMemcpyAsync(kst, kb + size_t(6) * L, sizeof(YPoint) * L, hipMemcpyDeviceToDevice, P->stream));
+            // first-same-as-last: k_0 already holds the last step's final stage (written on accept)
         } else {
             const YPoint* ycur = y0;
             int nb = c.M - 1;

@@ -172,7 +172,9 @@ def cpu_baseline(L: int, M: int, evals_per_step: float, budget_s: float = 20.0):
     per_eval = elapsed / done * L
     return {"value": 1.0 / (per_eval * evals_per_step), "unit": "steps/s", "cores": threads, "kind": "oracle",
             "sample": f"{done} rows ({done / L:.2f} right-hand-side evaluations) at L={L}, M={M} "
-                      f"(synthetic smooth history), {elapsed:.1f} s, scaled to {evals_per_step:.2f} evaluations per step"}
+                      f"(synthetic smooth history), {elapsed:.1f} s, scaled to {evals_per_step:.2f} evaluations per step; "
+                      f"the oracle as written, whose t-bracket search walks the stored slices one by one "
+                      f"(O(L^2 M) per evaluation)"}
 
 
 def sweep_requests(pk, n: int, seed: int, precision: int, tmax_range=(10.0, 100.0)):

@@ -135,3 +135,46 @@ def test_fluctuation_dissipation_plot_of_pure_p3():
         assert 0.3 < f["aging_slope"] < 0.607865
         assert 0.74 < f["break_C"] < 0.766911
     assert fits[1]["aging_slope"] > fits[0]["aging_slope"] and fits[1]["break_C"] > fits[0]["break_C"]
+
+
+def test_equilibrium_start_at_full_size():
+    """The equilibrium start of the CPU pins (pure p = 3, f = q^3/2, at T = 1 above
+    T_d, beta0 = 1/T: Sec. 2.1 with the forcing term), solved by the library on the
+    GPU at the L = 2048 grid to t = 6: E(t) = -f(1)/T and mu(t) = T + f'(1)/T at
+    every stored slice, C and R at fixed t - t' the same on every slice, and the FDT
+    R = -C'(tau)/T on a stored slice.  The bounds are a tenth of what the oracle
+    reaches at L = 96 (its discretisation error falls by more than 8x per doubling
+    of L), so a full-size adaptive run is held to the exact solution, not to a
+    second run of the same code."""
+    import oracle
+    L, T = 2048, 1.0
+    p = pk.make_params({3: 1.0}, T, beta0=1.0 / T, t_max=1e4, L=L, M_cap=4000, eps=1e-8, dt0=1e-3, dt_min=1e-12)
+    s = pk.Solver(p)
+    st, info = s.step(6.0)
+    assert st == pk.DONE or info.t >= 6.0 - 1e-12
+    t, E, mu = s.read(pk.F_T_GRID), s.read(pk.F_ENERGY), s.read(pk.F_MU)
+    C, R, dC, dR = (s.read(f) for f in (pk.F_C, pk.F_R, pk.F_DC, pk.F_DR))
+    thc = s.read(pk.F_THETA_C)
+    s.close()
+    M = t.size
+    say(f"equilibrium start at L={L}: {info.accepted} accepted, {info.rejected} rejected, M={M}")
+    eE = np.abs(E + 0.5 / T).max()
+    eM = np.abs(mu - T - 1.5 / T).max()
+    ts = oracle.ThetaSetup(L, 1e4)
+    eS = 0.0
+    for tau in (0.5, 1.0, 2.0):
+        vals = []
+        for n in range(M):
+            if t[n] < tau + 0.25:
+                continue
+            c = tau / t[n]
+            x = oracle.index_of(L, 1e4, 1.0 - c, c)
+            vals.append(oracle.hist_value(ts, t, C, R, dC, dR, M, t[-1], C[-1], R[-1], t[n], -1, x, 1.0 - c, c))
+        vals = np.array(vals)
+        eS = max(eS, np.ptp(vals[:, 0]), np.ptp(vals[:, 1]))
+    n = M - 2
+    tau = thc * t[n]
+    sel = (tau > 0.2) & (tau < 4.0)
+    eF = np.abs(R[n, sel] + dC[n, sel] / (thc[sel] * T)).max()
+    say(f"  |E + f(1)/T| {eE:.2e}, |mu - T - f'(1)/T| {eM:.2e}, stationarity {eS:.2e}, FDT {eF:.2e}")
+    assert eE < 3e-8 and eM < 1e-7 and eS < 3e-7 and eF < 3e-6

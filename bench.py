@@ -933,8 +933,11 @@ def main() -> int:
                     help="serving tick cost against the number of admitted solves (FP64, L=512 and 1024)")
     ap.add_argument("--pool-L", type=int, default=0, help="restrict --pool-ticks to one grid length")
     ap.add_argument("--pool-n", type=int, default=0, help="restrict --pool-ticks to one number of solves")
+    ap.add_argument("--no-ssprk-window", action="store_true",
+                    help="skip the SSPRK(10,4) window at the value window's end state")
     ap.add_argument("--no-long-window", action="store_true",
-                    help="skip the long window (for profiled runs: the value window is then the last "
+                    help="skip the long window and the SSPRK(10,4) window (for profiled runs: the value "
+                         "window is then the last "
                          "launches of the history-integral kernel)")
     ap.add_argument("--sparsify", action="store_true",
                     help="only the sparsification residual kernel at L=4096, M=4096 (one pass, nothing removed)")
@@ -998,6 +1001,8 @@ def main() -> int:
         "config": w["config"],
         "roofline": w["roofline"],
         "long_window": w["long_window"],
+        "ssprk_window": w["ssprk_window"],
+        "rhs_evals_per_s": w["steps_per_s"] * w["config"]["rhs_evals_per_step"],
     }
     calibration_copies(torch)
     if not args.no_compare:
@@ -1007,7 +1012,7 @@ def main() -> int:
                       "M_window": o["config"]["M_window"], "t_window": o["config"]["t_window"],
                       "rhs_evals_per_step": o["config"]["rhs_evals_per_step"],
                       "hist_integral_avg_launch_us": o["roofline"]["avg_launch_us"],
-                      "roofline": o["roofline"], "long_window": o["long_window"]}
+                      "roofline": o["roofline"], "long_window": o["long_window"], "ssprk_window": o["ssprk_window"]}
         if w["long_window"] and o["long_window"]:
             out[other]["long_window_speedup_vs_" + prec_name] = (o["long_window"]["stage_evals_per_s"] /
                                                                 w["long_window"]["stage_evals_per_s"])
@@ -1109,6 +1114,7 @@ def timed_window(pk, torch, prec_name: str, args) -> dict:
     alu = t_flops >= t_bytes
     log(f"window ({prec_name}): {steps} steps in {elapsed:.3f} s, hist_integral {avg_ms * 1e3:.1f} us/launch")
     scheme = lambda i: "SSPRK(10,4)" if i.scheme == pk.SCHEME_SSPRK104 else "DP5"
+    ssprk = None if (args.no_ssprk_window or args.no_long_window) else _ssprk_window(pk, torch, s, params, prec_name)
     long_window = None
     if not args.no_long_window:
         # the long window: three more sparsification passes
@@ -1154,6 +1160,7 @@ def timed_window(pk, torch, prec_name: str, args) -> dict:
             "kernel_ms_per_step": {name: v[1] / steps for name, v in k.items()},
         },
         "long_window": long_window,
+        "ssprk_window": ssprk,
         "roofline": {
             "kernel": "hist_integral",
             "bound": "alu" if alu else "hbm",
@@ -1174,6 +1181,34 @@ def timed_window(pk, torch, prec_name: str, args) -> dict:
                          "frac": tflops / PEAK_FP64_TFLOPS, "floor_us": t_flops * 1e6},
         },
     }
+
+
+def _ssprk_window(pk, torch, s, params, prec_name: str, steps: int = 100, warm: int = 10) -> dict:
+    """SSPRK(10,4) steps at the workload's own state: the history, state and step of the
+    solve just timed are loaded into a second solve of the same parameters with the
+    scheme set to SSPRK(10,4) (the scheme of the long-time regime, which the run
+    switches to once dt reaches DP5's stability boundary; a 4096-slice history does not
+    get there), which then takes `warm` untimed and `steps` timed steps: the same
+    kernels at ten stages per step instead of six."""
+    info = s.info()
+    nb = int(info.nb_valid)
+    t, C, R, dC, dR = (s.read(f) for f in (pk.F_T_GRID, pk.F_C, pk.F_R, pk.F_DC, pk.F_DR))
+    s2 = pk.Solver(params)
+    s2.set_history(t, C, R, dC, dR, nb=nb, dt=info.dt, scheme=pk.SCHEME_SSPRK104)
+    del C, R, dC, dR
+    s2.step(float("inf"), warm)
+    i0, i1, n, elapsed, k = _kernel_window(pk, torch, s2, steps=steps)
+    s2.close()
+    ev = i1.rhs_evals - i0.rhs_evals
+    assert i1.scheme == pk.SCHEME_SSPRK104
+    log(f"SSPRK window ({prec_name}): {n} steps in {elapsed:.3f} s, {ev / max(n, 1):.2f} evaluations per step, "
+        f"t {i0.t:.5g} -> {i1.t:.5g}, dt {i1.dt:.3g}")
+    return {"what": "SSPRK(10,4) steps from the value window's end state (history, state and dt loaded into a "
+                    "second solve with the scheme set to SSPRK(10,4))",
+            "steps": int(n), "seconds": elapsed, "steps_per_s": n / elapsed, "stage_evals_per_s": ev / elapsed,
+            "rhs_evals_per_step": ev / max(n, 1), "t_window": [i0.t, i1.t], "M_window": [int(i0.M), int(i1.M)],
+            "dt_end": i1.dt, "accepted": int(i1.accepted - i0.accepted), "rejected": int(i1.rejected - i0.rejected),
+            "hist_integral_avg_launch_us": k["hist_integral"][1] / max(k["hist_integral"][0], 1) * 1e3}
 
 
 def _gamma_of(tmax: float) -> float:

@@ -347,8 +347,9 @@ def c4_sweep(pk, torch, n: int = 128, tmax_range=(1e2, 1e3), seed: int = 2026040
 def pool_ticks(pk, torch, Ls=(512, 1024), ns=(1, 4, 16, 64, 128), ticks: int = 300, solo: bool = True) -> dict:
     """Cost of one serving tick against the number of admitted solves (FP64, 2+3+4 model,
     a_p^2 = 0.3, 0.4, 0.3, T = 0.8, history cap L, eps = 1e-6): wall time per tick (one RK
-    stage of every solve: the batched launches, the descriptor upload, one synchronisation
-    and the host controller) and per stage evaluation, after 120 untimed ticks; beside it
+    stage evaluation of every solve: the batched launches, the descriptor upload, one
+    synchronisation and the host controller) and per stage evaluation (counted from the
+    solves' own counters), after 120 untimed ticks; beside it
     one solve stepped alone (wall and kernel time per stage, from the library's HIP
     events).  Under rocprofv3 --kernel-trace, a run restricted to one L and one count
     (which skips the solve alone) gives the GPU time per tick; the rest of the wall time
@@ -363,17 +364,18 @@ def pool_ticks(pk, torch, Ls=(512, 1024), ns=(1, 4, 16, 64, 128), ticks: int = 3
             log(f"pool ticks L={L}: one solve alone {solo_row['solo_wall_us_per_stage']:.1f} us per stage")
         for n in ns:
             pool = pk.Pool(n * pk.dmfe_footprint(p) + (1 << 20), max_instances=max(n, 1))
-            for _ in range(n):
-                pool.submit(p)
+            ids = [pool.submit(p) for _ in range(n)]
             pool.run(120)
+            ev0 = sum(int(pool.result(r)[0].rhs_evals) for r in ids)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             st = pool.run(ticks)
             torch.cuda.synchronize()
             wall = time.perf_counter() - t0
+            evals = sum(int(pool.result(r)[0].rhs_evals) for r in ids) - ev0
             pool.close()
-            row = {**solo_row, "instances": n, "us_per_tick": wall / ticks * 1e6,
-                   "us_per_stage_eval": wall / ticks / n * 1e6, "running_at_end": int(st.running)}
+            row = {**solo_row, "instances": n, "us_per_tick": wall / ticks * 1e6, "stage_evals": evals,
+                   "us_per_stage_eval": wall / evals * 1e6, "running_at_end": int(st.running)}
             if solo:
                 row["pooled_vs_alone_per_stage"] = solo_row["solo_wall_us_per_stage"] / row["us_per_stage_eval"]
             out["rows"].append(row)

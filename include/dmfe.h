@@ -365,8 +365,9 @@ dmfe_status dmfe_snapshot_save(dmfe_handle *h, const char *path, int32_t theta_s
  * together on one device.  Requests queue on submit and are admitted while a
  * slot is free and their footprint (dmfe_footprint) fits in the pool's arena;
  * admitted solves keep their history resident and advance together, one RK
- * stage per tick, each phase of a tick being one batched launch over all of
- * them (uneven L and M per solve).  Finished solves keep their memory until
+ * stage evaluation per tick (DP5's first stage, the last stage of the step
+ * before, takes none: its second runs in the same tick), each phase of a tick
+ * being one batched launch over all of them (uneven L and M per solve).  Finished solves keep their memory until
  * dmfe_pool_release, so results can be read; released memory admits queued
  * requests.  All solves of a pool use the same history precision and s = 10.
  */

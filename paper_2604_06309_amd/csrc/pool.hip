@@ -205,6 +205,9 @@ dmfe_status tick(dmfe_pool* P) {
         }
         auto& c = h->cur;
         const Tableau& T = *c.T;
+        // first-same-as-last: k_0 already holds the last step's final stage (written on accept),
+        // so the step's first stage needs no work and its second runs in this tick
+        if (c.st == 0 && h->fsal_valid) c.st = 1;
         const int L = h->L, st = c.st;
         YPoint* y0 = h->at<YPoint>(h->lo.y);
         YPoint* ys = h->at<YPoint>(h->lo.ys);
@@ -212,45 +215,41 @@ dmfe_status tick(dmfe_pool* P) {
         YPoint* kst = kb + size_t(st) * L;
         const double tst = c.tn + T.c[st] * c.dt;
         if (fp32 < 0) fp32 = h->fp32;
-        if (st == 0 && h->fsal_valid) {
-            // first-same-as-last: k_0 already holds the last step's final stage (written on accept)
-        } else {
-            const YPoint* ycur = y0;
-            int nb = c.M - 1;
-            void* store = slot_ptr(h, h->slot[c.M - 1]);
-            if (st > 0) {
-                CombineDesc& cd = a_comb[n_comb];
-                cd.y0 = y0;
-                cd.k = kb;
-                cd.ys = ys;
-                cd.L = L;
-                cd.nk = st;
-                cd.dt = c.dt;
-                for (int l = 0; l < 10; ++l) cd.a[l] = l < st ? T.A[st][l] : 0.0;
-                a_fbc[n_comb] = comb_blocks;
-                comb_blocks += (L + kCombineBlock - 1) / kCombineBlock;
-                ++n_comb;
-                ycur = ys;
-                nb = c.M;
-                store = (T.fsal && st == T.S - 1) ? slot_ptr(h, c.next_slot) : nullptr;
-            }
-            PrepDesc& pd = a_prep[n_eval];
-            pd.y = ycur;
-            pd.nu = h->at<double>(h->lo.nu);
-            pd.mue = h->at<double>(h->lo.mue);
-            pd.stage = stage_slot(h);
-            pd.L = L;
-            pd.fp32 = h->fp32;
-            pd.t = tst;
-            pd.m = h->m;
-            a_args[n_eval] = stage_args(h, tst, nb, ycur, kst, store);
-            a_fbh[n_eval] = hist_blocks;
-            hist_blocks += (L + kHistRowsPerBlock - 1) / kHistRowsPerBlock;
-            nb_max = std::max(nb_max, nb);
-            pmax = std::max(pmax, h->m.pmax);
-            ++n_eval;
-            h->rhs_evals += 1;
+        const YPoint* ycur = y0;
+        int nb = c.M - 1;
+        void* store = slot_ptr(h, h->slot[c.M - 1]);
+        if (st > 0) {
+            CombineDesc& cd = a_comb[n_comb];
+            cd.y0 = y0;
+            cd.k = kb;
+            cd.ys = ys;
+            cd.L = L;
+            cd.nk = st;
+            cd.dt = c.dt;
+            for (int l = 0; l < 10; ++l) cd.a[l] = l < st ? T.A[st][l] : 0.0;
+            a_fbc[n_comb] = comb_blocks;
+            comb_blocks += (L + kCombineBlock - 1) / kCombineBlock;
+            ++n_comb;
+            ycur = ys;
+            nb = c.M;
+            store = (T.fsal && st == T.S - 1) ? slot_ptr(h, c.next_slot) : nullptr;
         }
+        PrepDesc& pd = a_prep[n_eval];
+        pd.y = ycur;
+        pd.nu = h->at<double>(h->lo.nu);
+        pd.mue = h->at<double>(h->lo.mue);
+        pd.stage = stage_slot(h);
+        pd.L = L;
+        pd.fp32 = h->fp32;
+        pd.t = tst;
+        pd.m = h->m;
+        a_args[n_eval] = stage_args(h, tst, nb, ycur, kst, store);
+        a_fbh[n_eval] = hist_blocks;
+        hist_blocks += (L + kHistRowsPerBlock - 1) / kHistRowsPerBlock;
+        nb_max = std::max(nb_max, nb);
+        pmax = std::max(pmax, h->m.pmax);
+        ++n_eval;
+        h->rhs_evals += 1;
         c.st = st + 1;
         if (c.st == T.S) {
             FinishDesc& fd = a_fin[n_fin];

@@ -298,6 +298,12 @@ void dmfe_destroy(dmfe_handle *h);
  */
 enum { DMFE_K_HIST_INTEGRAL = 0, DMFE_K_STAGE_PREP = 1, DMFE_K_RK = 2, DMFE_K_SPARSIFY = 3, DMFE_K_COUNT = 4 };
 dmfe_status dmfe_timing(dmfe_handle *h, int32_t enable);
+/* Which kernels dmfe_timing times: bit k of mask for kernel id k (default: all).
+ * Each timed launch adds two event records to the stream, about 5% of an RK
+ * step at L = 4096 when every kernel is timed; timing the history-integral
+ * kernel alone costs a third of that.  Infrastructure, not a step of the
+ * method.  Returns DMFE_ERR_INVALID for bits outside the kernel ids. */
+dmfe_status dmfe_timing_select(dmfe_handle *h, uint32_t mask);
 dmfe_status dmfe_timing_read(dmfe_handle *h, int32_t kernel, int64_t *launches, double *total_ms,
                              int64_t *slices_read);
 

@@ -33,6 +33,7 @@ INTERP_INDEX_LAGRANGE, INTERP_THETA_LAGRANGE, INTERP_INDEX_FH, INTERP_THETA_FH =
 SCHEME_DP5, SCHEME_SSPRK104 = 0, 1
 F_T_GRID, F_THETA, F_THETA_C, F_NU, F_C, F_R, F_DC, F_DR, F_ENERGY, F_MU = range(10)
 K_HIST_INTEGRAL, K_STAGE_PREP, K_RK, K_SPARSIFY = range(4)
+K_COUNT = 4
 
 
 class dmfe_params(ctypes.Structure):
@@ -105,6 +106,7 @@ SIGNATURES = {
     "dmfe_control_update": (_i32, [ctypes.POINTER(dmfe_control), _d, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "dmfe_sparsify_select": (_i32, [_vp, _i64, _i64, _d, _vp, ctypes.POINTER(_i64)]),
     "dmfe_timing": (_i32, [_vp, _i32]),
+    "dmfe_timing_select": (_i32, [_vp, ctypes.c_uint32]),
     "dmfe_checkpoint_save": (_i32, [_vp, ctypes.c_char_p, _i32]),
     "dmfe_checkpoint_wait": (_i32, [_vp]),
     "dmfe_checkpoint_load": (_i32, [ctypes.c_char_p, ctypes.POINTER(dmfe_resources), ctypes.POINTER(_vp)]),
@@ -277,6 +279,14 @@ def dmfe_rhs_noalloc(h: int, t: float, yC, yR, nb: int, outC, outR):
 
 def dmfe_timing(h: int, enable: bool) -> None:
     _check(lib().dmfe_timing(h, int(enable)), "dmfe_timing")
+
+
+def dmfe_timing_select(h: int, kernels) -> None:
+    """Time only the given kernel ids (K_*) while timing is on."""
+    mask = 0
+    for k in kernels:
+        mask |= 1 << int(k)
+    _check(lib().dmfe_timing_select(h, mask), "dmfe_timing_select")
 
 
 def dmfe_timing_read(h: int, kernel: int) -> tuple[int, float, int]:
@@ -574,7 +584,10 @@ class Solver:
     def rhs(self, t: float, yC, yR, nb: int):
         return dmfe_rhs(self.h, t, yC, yR, nb)
 
-    def timing(self, enable: bool) -> None:
+    def timing(self, enable: bool, kernels=None) -> None:
+        """Per-launch HIP events on (of the given kernel ids only, default all) or off."""
+        if enable:
+            dmfe_timing_select(self.h, range(K_COUNT) if kernels is None else kernels)
         dmfe_timing(self.h, enable)
 
     def timing_read(self, kernel: int) -> tuple[int, float, int]:

@@ -232,7 +232,7 @@ dmfe_status fail_msg(dmfe_status s, const std::string& msg) {
 
 // Event pair around one launch when timing is on; nullptr otherwise.
 dmfe_handle::EvPair* timing_begin(dmfe_handle* h, int kernel, int64_t slices) {
-    if (!h->timing) return nullptr;
+    if (!h->timing || !((h->timing_mask >> kernel) & 1u)) return nullptr;
     dmfe_handle::EvPair p;
     if (!h->ev_pool.empty()) {
         p = h->ev_pool.back();
@@ -1192,6 +1192,12 @@ dmfe_status dmfe_timing(dmfe_handle* h, int32_t enable) {
         }
     }
     h->timing = enable != 0;
+    return DMFE_OK;
+}
+
+dmfe_status dmfe_timing_select(dmfe_handle* h, uint32_t mask) {
+    if (!h || (mask >> DMFE_K_COUNT) != 0) return DMFE_ERR_INVALID;
+    h->timing_mask = mask;
     return DMFE_OK;
 }
 

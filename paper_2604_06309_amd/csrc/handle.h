@@ -72,6 +72,7 @@ struct dmfe_handle {
         int64_t slices = 0;
     };
     bool timing = false;
+    uint32_t timing_mask = (1u << DMFE_K_COUNT) - 1;  // kernels timed when timing is on
     int64_t kt_launches[DMFE_K_COUNT] = {};
     double kt_ms[DMFE_K_COUNT] = {};
     int64_t kt_slices[DMFE_K_COUNT] = {};

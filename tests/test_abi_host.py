@@ -175,6 +175,14 @@ def test_sparsify_select_matches_oracle(lib):
         assert n1 == n2 and np.array_equal(d1, d2)
 
 
+def test_timing_calls_need_a_handle(lib):
+    """The timing entry points refuse a null handle (host checks, no device call)."""
+    assert lib.dmfe_timing(None, 1) == pk.ERR_INVALID
+    assert lib.dmfe_timing_select(None, 1) == pk.ERR_INVALID
+    n, ms, sl = ctypes.c_int64(), ctypes.c_double(), ctypes.c_int64()
+    assert lib.dmfe_timing_read(None, 0, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(sl)) == pk.ERR_INVALID
+
+
 def test_param_record_needs_a_handle(lib):
     need = ctypes.c_size_t(7)
     assert lib.dmfe_param_record(None, None, 0, ctypes.byref(need)) == pk.ERR_INVALID

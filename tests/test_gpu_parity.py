@@ -257,6 +257,32 @@ def test_workspace_and_stream():
     b.close()
 
 
+def test_timing_of_selected_kernels():
+    """Per-launch timing counts launches of the selected kernels only (DP5: six
+    history-integral launches per step, the first stage reused from the step
+    before), and timing does not change the results."""
+    say("timing selection")
+    p = pk.make_params({3: 0.5, 4: 0.5}, 0.6, t_max=1e4, L=64, M_cap=400, eps=1e-8, dt0=1e-3)
+    a, b = pk.Solver(p), pk.Solver(p)
+    a.step(1.0)
+    b.step(1.0)
+    e0 = a.info().rhs_evals
+    a.timing(True, [pk.K_HIST_INTEGRAL])
+    b.timing(True)
+    _, ia = a.step(float("inf"), 10)
+    b.step(float("inf"), 10)
+    na, msa, _ = a.timing_read(pk.K_HIST_INTEGRAL)
+    assert na == ia.rhs_evals - e0 and na > 0 and msa > 0.0
+    assert a.timing_read(pk.K_RK)[0] == 0 and a.timing_read(pk.K_STAGE_PREP)[0] == 0
+    assert b.timing_read(pk.K_RK)[0] > 0 and b.timing_read(pk.K_STAGE_PREP)[0] == b.timing_read(pk.K_HIST_INTEGRAL)[0]
+    assert na == b.timing_read(pk.K_HIST_INTEGRAL)[0]
+    np.testing.assert_array_equal(a.read(pk.F_C), b.read(pk.F_C))
+    with pytest.raises(pk.DmfeError):
+        pk.dmfe_timing_select(a.h, [pk.K_COUNT])
+    a.close()
+    b.close()
+
+
 def test_errors_from_device_calls():
     say("error paths")
     p = pk.make_params({3: 0.5, 4: 0.5}, 0.6, t_max=1e4, L=64, M_cap=16, eps=1e-30, dt0=1e-3)

@@ -437,10 +437,12 @@ __device__ __forceinline__ int bracket_fast(const double* t, const int* bk, cons
 // Each wavefront iteration covers a tile of kRowsPerWave rows x (64 /
 // kRowsPerWave) consecutive nodes i; the block's waves split its rows into
 // groups of kRowsPerWave and the nodes into `phases` interleaved sets, so one
-// block iteration covers all its rows x (8 x phases) nodes.  Tiles of several
+// block iteration covers all its rows x (16 x phases) nodes.  Tiles of several
 // rows keep the 2-D stencil gathers of one instruction within fewer cache lines
-// (neighbouring rows read neighbouring history points).
-constexpr int kRowsPerWave = 8;
+// (neighbouring rows read neighbouring history points).  Blocks of 4 rows (1024
+// at L = 4096, four per CU in turn) even out the launch's tail better than
+// blocks of 8: rows below theta = 1/2 cost up to twice the others.
+constexpr int kRowsPerWave = 4;
 static_assert(kRowsPerBlock % kRowsPerWave == 0, "rows per wave");
 constexpr int kColsPerWave = kWave / kRowsPerWave;
 constexpr int kGroups = kRowsPerBlock / kRowsPerWave;  // row groups of a block
@@ -741,8 +743,9 @@ __device__ __forceinline__ void hist_integral_block(const StageArgs& a, int row_
                 double c0, r0, dc0, dr0, c1, r1, dc1, dr1;
                 if constexpr (kShared) {
                     // Every lane active (a ragged last tile is not), one slot pair for the whole
-                    // wave, and every stencil within kTileNodes nodes of lane 7's, the smallest
-                    // base of the tile (psi falls with theta_i and rises with theta_j).
+                    // wave, and every stencil within kTileNodes nodes of the base of the lane on the
+                    // tile's first row and last node, the smallest base of the tile (psi falls with
+                    // theta_i and rises with theta_j).
                     const int k0 = __builtin_amdgcn_readfirstlane(key);
                     const int bmin = __builtin_amdgcn_readlane(base, kColsPerWave - 1);
                     const int off = base - bmin;

@@ -173,7 +173,8 @@ hipError_t launch_hist_integral_multi(const StageArgs* d, const int* first_block
                                       int pmax, int fp32, int nb_max, hipStream_t st);
 hipError_t launch_rk_finish_multi(const FinishDesc* d, int n, hipStream_t st);
 constexpr int kCombineBlock = 256;
-constexpr int kHistRowsPerBlock = 4;
+// Rows of the theta grid per history-integral block: 4 with an FP64 history, 8 with FP32.
+constexpr int hist_rows_per_block(int fp32) { return fp32 ? 8 : 4; }
 
 // ---------------------------------------------------------------- uniform mode (kernels_uniform.hip)
 struct UniArgs {

@@ -410,7 +410,6 @@ __global__ __launch_bounds__(1024) void k_stage_prep_multi(const PrepDesc* __res
 // search in double precision between the brackets of neighbouring bucket
 // edges, so the result is exact whatever the rounding of the bucket index.
 constexpr int kBuckets = 512;
-constexpr int kRowsPerBlock = kHistRowsPerBlock;
 
 struct Buckets {
     float lt1, inv;  // log2 t_1, K / span
@@ -433,19 +432,23 @@ __device__ __forceinline__ int bracket_fast(const double* t, const int* bk, cons
     return bracket(t, lo, hi, s);
 }
 
-// Pair tiles.  A block owns kRowsPerBlock consecutive rows j (t' = theta_j t).
-// Each wavefront iteration covers a tile of kRowsPerWave rows x (64 /
-// kRowsPerWave) consecutive nodes i; the block's waves split its rows into
-// groups of kRowsPerWave and the nodes into `phases` interleaved sets, so one
-// block iteration covers all its rows x (16 x phases) nodes.  Tiles of several
+// Pair tiles.  A block owns `rows` consecutive rows j (t' = theta_j t).  Each
+// wavefront iteration covers a tile of rows_wave rows x (64 / rows_wave)
+// consecutive nodes i; the block's waves split its rows into groups of
+// rows_wave and the nodes into `phases` interleaved sets, so one block
+// iteration covers all its rows x (cols_wave x phases) nodes.  Tiles of several
 // rows keep the 2-D stencil gathers of one instruction within fewer cache lines
-// (neighbouring rows read neighbouring history points).  Blocks of 4 rows (1024
-// at L = 4096, four per CU in turn) even out the launch's tail better than
-// blocks of 8: rows below theta = 1/2 cost up to twice the others.
-constexpr int kRowsPerWave = 4;
-static_assert(kRowsPerBlock % kRowsPerWave == 0, "rows per wave");
-constexpr int kColsPerWave = kWave / kRowsPerWave;
-constexpr int kGroups = kRowsPerBlock / kRowsPerWave;  // row groups of a block
+// (neighbouring rows read neighbouring history points).  FP64 history: blocks of
+// 4 rows (1024 at L = 4096, four per CU in turn), which even out the launch's
+// tail better than blocks of 8 (rows below theta = 1/2 cost up to twice the
+// others); FP32 history: blocks of 8 rows, whose costs differ less.
+template <class HP> struct RowTiles {
+    static constexpr int rows = hist_rows_per_block(sizeof(HP) == sizeof(HPoint32) ? 1 : 0);
+    static constexpr int rows_wave = rows;
+    static constexpr int cols_wave = kWave / rows_wave;
+    static constexpr int groups = rows / rows_wave;  // row groups of a block
+    static_assert(rows % rows_wave == 0 && kWave % rows_wave == 0, "tile shape");
+};
 
 
 // Tile configuration per history storage type, chosen by measurement at the
@@ -470,7 +473,9 @@ template <> struct HistCfg<HPoint32, 0> {
     static constexpr int phases = 12;
     static constexpr bool d_first = true;
 };
-template <class HP, int VAR = 0> constexpr int hist_threads() { return kGroups * HistCfg<HP, VAR>::phases * kWave; }
+template <class HP, int VAR = 0> constexpr int hist_threads() {
+    return RowTiles<HP>::groups * HistCfg<HP, VAR>::phases * kWave;
+}
 
 // Per pair (i, j) the kernel forms
 //   a = (C,R)(t, theta_i theta_j t)        index Lagrange on the stage slice
@@ -500,11 +505,11 @@ template <class HP, int VAR> constexpr bool shared_nodes() { return VAR == 0; }
 template <class HP, int VAR = 0>
 __host__ __device__ inline size_t lds_offset_tile(int nb, int L, bool yl) {
     constexpr int ph = HistCfg<HP, VAR>::phases;
-    return lds_offset_red(nb, L, yl) + (ph > 1 ? size_t(kRowsPerBlock) * ph * 9 * 8 : 0);
+    return lds_offset_red(nb, L, yl) + (ph > 1 ? size_t(RowTiles<HP>::rows) * ph * 9 * 8 : 0);
 }
 template <class HP, int VAR = 0>
 __host__ __device__ inline size_t lds_bytes(int nb, int L, bool yl) {
-    constexpr int waves = kGroups * HistCfg<HP, VAR>::phases;
+    constexpr int waves = RowTiles<HP>::groups * HistCfg<HP, VAR>::phases;
     return lds_offset_tile<HP, VAR>(nb, L, yl) +
            (shared_nodes<HP, VAR>() ? size_t(waves) * 2 * kTileNodes * sizeof(HPoint) : 0);
 }
@@ -519,6 +524,7 @@ __device__ __forceinline__ void hist_integral_block(const StageArgs& a, int row_
     // error estimate.)
     using HS = hreal_t<HP>;  // storage type of the history
     constexpr int kPhases = HistCfg<HP, VAR>::phases;
+    constexpr int kGroups = RowTiles<HP>::groups, kColsPerWave = RowTiles<HP>::cols_wave;
     constexpr int kColStride = kColsPerWave * kPhases;  // nodes one block iteration covers
     extern __shared__ double smem[];
     const int nb = a.nb;
@@ -561,8 +567,8 @@ __device__ __forceinline__ void hist_integral_block(const StageArgs& a, int row_
     const int wave = threadIdx.x / kWave;
     const int grp = wave % kGroups, ph = wave / kGroups;
     const int r = lane / kColsPerWave, cl = lane % kColsPerWave;
-    const int row = grp * kRowsPerWave + r;  // row within the block
-    const int jr = row_block * kRowsPerBlock + row;
+    const int row = grp * RowTiles<HP>::rows_wave + r;  // row within the block
+    const int jr = row_block * RowTiles<HP>::rows + row;
     if (kPhases == 1 && jr >= L) return;     // whole wave past the end (no later barrier)
     const bool valid = jr < L;
     const int j = valid ? jr : L - 1;
@@ -1281,7 +1287,7 @@ static void launch_gen_var(const StageArgs& a, dim3 grid, hipStream_t st) {
 }
 template <int S, class HP, bool YL>
 static void launch_hi_shy(const StageArgs& a, size_t lds, hipStream_t st) {
-    const dim3 grid(nblk(a.L, kRowsPerBlock)), block(hist_threads<HP>());
+    const dim3 grid(nblk(a.L, RowTiles<HP>::rows)), block(hist_threads<HP>());
     if (a.interp != DMFE_INTERP_INDEX_LAGRANGE || a.log_r) {
         launch_gen_var<S, HP, YL, false>(a, grid, st);
     } else if (a.m.pmax <= 4) {
@@ -1304,7 +1310,7 @@ static hipError_t launch_hi_sh(const StageArgs& a, hipStream_t st) {
         // more stored slices than LDS holds times for (about 19K with 160 KB of LDS): they are read from
         // global memory
         const size_t lds = lds_bytes<HP>(0, a.L, false);
-        const dim3 grid(nblk(a.L, kRowsPerBlock)), block(hist_threads<HP>());
+        const dim3 grid(nblk(a.L, RowTiles<HP>::rows)), block(hist_threads<HP>());
         if (a.interp != DMFE_INTERP_INDEX_LAGRANGE || a.log_r) {
             launch_gen_var<S, HP, false, true>(a, grid, st);
         } else if (a.m.pmax <= 4) {

@@ -245,7 +245,7 @@ dmfe_status tick(dmfe_pool* P) {
         pd.m = h->m;
         a_args[n_eval] = stage_args(h, tst, nb, ycur, kst, store);
         a_fbh[n_eval] = hist_blocks;
-        hist_blocks += (L + kHistRowsPerBlock - 1) / kHistRowsPerBlock;
+        hist_blocks += (L + hist_rows_per_block(h->fp32) - 1) / hist_rows_per_block(h->fp32);
         nb_max = std::max(nb_max, nb);
         pmax = std::max(pmax, h->m.pmax);
         ++n_eval;

@@ -85,7 +85,7 @@ enum {
  * adaptive mode:
  *   L                   theta-grid length (2s <= L <= 16384)
  *   M_cap               history capacity in slices (0 means L): 16 <= M_cap <= 65536 (above about
- *                       16.7K stored slices with an FP64 history, 19.6K with FP32, the history-integral
+ *                       17.1K stored slices with an FP64 history, 16.7K with FP32, the history-integral
  *                       kernel reads their times from global memory instead of LDS); <= 16384 in the
  *                       serving pool
  *   eps                 tolerance on the 1-norm RK error (Sec. 3.5); sparsification drops

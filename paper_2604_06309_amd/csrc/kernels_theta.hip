@@ -639,9 +639,31 @@ __device__ __forceinline__ void hist_integral_block(const StageArgs& a, int row_
     double c0C = 0.0;
     int mprev = 0;  // FP32 history: this lane's last bracket (its targets s = phi t grow with i)
     const int i0 = cl + kColsPerWave * ph;
+    // theta_i and the 2-D coordinate, which start each iteration's dependent chain (the
+    // bracket search, then the 2-D stencil), are loaded one iteration ahead (the last
+    // iteration reloads node L-1, unused).  Default stencil of up to 10 points only, and
+    // not for an FP32 history with the stage slice in global memory: elsewhere the two
+    // registers it holds would spill.
+    constexpr bool kAhead = kShared && S <= 10 && (sizeof(HS) == 8 || YL);
+    double th_next = 0.0, xd_next = 0.0;
+    if constexpr (kAhead) {
+        th_next = a.th[i0 < L ? i0 : L - 1];
+        xd_next = Xdj[i0 < L ? i0 : L - 1];
+    }
 #pragma unroll 1
     for (int i = i0; i < L; i += kColStride) {
-        const double thi = a.th[i], w = a.nu[i], xa = Xa[i], xb = Xb[L - 1 - i], xd = Xdj[i];
+        double thi, xd;
+        if constexpr (kAhead) {
+            thi = th_next;
+            xd = xd_next;
+            const int inext = i + kColStride < L ? i + kColStride : L - 1;
+            th_next = a.th[inext];
+            xd_next = Xdj[inext];
+        } else {
+            thi = a.th[i];
+            xd = Xdj[i];
+        }
+        const double w = a.nu[i], xa = Xa[i], xb = Xb[L - 1 - i];
         double wl[S];
         const double phi = fma(thcj, thi, thj);
         double aC, aR, bC, bR, cC, cR, dC, dR;
@@ -752,6 +774,7 @@ __device__ __forceinline__ void hist_integral_block(const StageArgs& a, int row_
                     // wave, and every stencil within kTileNodes nodes of the base of the lane on the
                     // tile's first row and last node, the smallest base of the tile (psi falls with
                     // theta_i and rises with theta_j).
+                    __builtin_amdgcn_s_setprio(0);  // the chain is done (raised in the loop below)
                     const int k0 = __builtin_amdgcn_readfirstlane(key);
                     const int bmin = __builtin_amdgcn_readlane(base, kColsPerWave - 1);
                     const int off = base - bmin;
@@ -797,6 +820,10 @@ __device__ __forceinline__ void hist_integral_block(const StageArgs& a, int row_
             }
         };
         if constexpr (HistCfg<HP, VAR>::d_first) {
+            // the wave issues ahead of the block's other waves on its SIMD until its 2-D
+            // stencil's addresses are known: the bracket search and the slot indices are a
+            // chain of dependent reads, and its loads then go out sooner
+            if constexpr (kShared) __builtin_amdgcn_s_setprio(2);
             fam_d();
             fam_abc();
         } else {

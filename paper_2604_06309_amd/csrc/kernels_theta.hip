@@ -177,14 +177,15 @@ __device__ __forceinline__ void interp4(const HP* row, int base, const R (&w)[S]
 // within 160 KB with the times of 16384 slices beside it.
 constexpr int kTileNodes = 28;
 
-// The 2-D stencil of one target on two slots, read in batches of 5 points (10 loads
-// in flight per lane before the first product), values widened to FP64 as they are
-// used, sums in the order of interp4.
+// The 2-D stencil of one target on two slots, read in batches of 5 points of an FP64
+// history (10 loads in flight per lane before the first product) or 10 of an FP32
+// history (the same 40 registers; 5 for stencils above 14 points, whose registers
+// would spill), values widened to FP64 as they are used, sums in the order of interp4.
 template <int S, class HP>
 __device__ __forceinline__ void gathered_stencil(const HP* p0, const HP* p1, int base, const double (&w)[S],
                                                  double& c0, double& r0, double& dc0, double& dr0, double& c1,
                                                  double& r1, double& dc1, double& dr1) {
-    constexpr int B = 5;
+    constexpr int B = sizeof(HP) == sizeof(HPoint) || S > 14 ? 5 : 10;
     c0 = r0 = dc0 = dr0 = c1 = r1 = dc1 = dr1 = 0.0;
 #pragma unroll
     for (int kb = 0; kb < 2 * S; kb += B) {

@@ -187,7 +187,8 @@ dmfe_status validate(const dmfe_params* p) {
     if (p->log_r != 0 && p->log_r != 1) return DMFE_ERR_INVALID;
     if (p->L < std::max(2 * s, 16) || p->L > 16384) return DMFE_ERR_INVALID;
     const int Mc = p->M_cap == 0 ? p->L : p->M_cap;
-    // beyond the ~19K slice times that LDS holds, the history-integral kernel reads them from global memory
+    // beyond the slice times that LDS holds (about 17K with the default stencil, 20K with the others),
+    // the history-integral kernel reads them from global memory
     if (Mc < 16 || Mc > 65536) return DMFE_ERR_INVALID;
     if (!(p->t_max > std::exp(1.0)) || !std::isfinite(p->t_max)) return DMFE_ERR_INVALID;
     if (!(p->eps > 0.0) || !(p->dt0 > 0.0) || !(p->dt_min >= 0.0) || p->dt_min >= p->dt0) return DMFE_ERR_INVALID;

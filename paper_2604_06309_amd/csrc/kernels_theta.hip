@@ -1335,8 +1335,8 @@ static hipError_t launch_hi_sh(const StageArgs& a, hipStream_t st) {
     } else if (without_y <= max_lds()) {
         launch_hi_shy<S, HP, false>(a, without_y, st);
     } else {
-        // more stored slices than LDS holds times for (about 19K with 160 KB of LDS): they are read from
-        // global memory
+        // more stored slices than LDS holds times for (with 160 KB of LDS, about 17K with the default
+        // stencil, 20K with the others): they are read from global memory
         const size_t lds = lds_bytes<HP>(0, a.L, false);
         const dim3 grid(nblk(a.L, RowTiles<HP>::rows)), block(hist_threads<HP>());
         if (a.interp != DMFE_INTERP_INDEX_LAGRANGE || a.log_r) {

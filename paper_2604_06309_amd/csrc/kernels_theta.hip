@@ -642,9 +642,9 @@ __device__ __forceinline__ void hist_integral_block(const StageArgs& a, int row_
     const int i0 = cl + kColsPerWave * ph;
     // theta_i and the 2-D coordinate, which start each iteration's dependent chain (the
     // bracket search, then the 2-D stencil), are loaded one iteration ahead (the last
-    // iteration reloads node L-1, unused).  Default stencil of up to 10 points only, and
-    // not for an FP32 history with the stage slice in global memory: elsewhere the two
-    // registers it holds would spill.
+    // iteration reloads node L-1, unused).  Default stencil of up to 10 points only (wider
+    // ones have no two registers to spare), and not for an FP32 history with the stage
+    // slice in global memory, where it measured about 1% slower.
     constexpr bool kAhead = kShared && S <= 10 && (sizeof(HS) == 8 || YL);
     double th_next = 0.0, xd_next = 0.0;
     if constexpr (kAhead) {
